@@ -1,0 +1,54 @@
+// Internal declarations shared by the host code and the HIP kernels of
+// libpdbm.  Not part of the public ABI (include/pdbm.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pdbm.h"
+
+namespace pdbm {
+
+constexpr int NQ = 33;          // D2V33: rest particle + 4 speeds x 8 directions
+constexpr int BLOCK = 256;      // threads per workgroup of the cell kernels
+constexpr int HIST_CAP = 4096;  // drift reports kept per solve
+constexpr int NXCD = 8;         // accelerator complex dies of an MI355X
+
+// Everything a kernel needs to know about one solve.  Passed by value as a
+// kernel argument (one solve per launch) or read from a device table (packed
+// launches over many solves).
+struct SolveDesc {
+    const void *f_in;  // [NQ][nr][pitch] of float or double
+    void *f_out;
+    const double *lam_in;  // [nr][pitch]
+    double *lam_out;
+    const double2 *cs;  // [ntheta] (cos theta_j, sin theta_j)
+    int32_t nr, nt, pitch, sector;
+    int32_t m, n, disc, reacts;  // disc: r_min == 0; reacts: w1+w2 > 0
+    int64_t plane;               // nr * pitch, elements per velocity plane
+    double r_min, dr, dth;
+    double dt_dr, dt_dth;  // dt/dr, dt/dtheta
+    double omega;          // exp(-dt/tau)
+    double w1, w2, Q, T_th, dt;
+    double A[16];  // F_k(T) = sum_n A[(k-1)*4+n-1] T^n
+};
+
+// Drift-report reduction state of one solve.
+struct DiagCtl {
+    double *partials;    // [nblocks][5]
+    unsigned *counter;   // blocks finished, reset by the last one
+    pdbm_diag *out;      // where the final record goes
+    int64_t step;        // step count of the reduced state
+    int32_t enabled;
+    int32_t pad;
+};
+
+// Kernel launchers (pdbm_kernels.hip).  All enqueue on `st` and return the
+// hipError_t of the launch.
+hipError_t launch_step(const SolveDesc &d, bool fp32, const DiagCtl &dc, hipStream_t st);
+hipError_t launch_init_ic(const SolveDesc &d, bool fp32, const pdbm_ic &ic, hipStream_t st);
+hipError_t launch_init_fields(const SolveDesc &d, bool fp32, const double *fields, hipStream_t st);
+hipError_t launch_moments(const SolveDesc &d, bool fp32, double *out, const DiagCtl &dc, hipStream_t st);
+int cell_blocks(const SolveDesc &d);
+
+}  // namespace pdbm

@@ -1,0 +1,489 @@
+// HIP kernels of libpdbm for gfx950 (MI355X).
+//
+// One cell per lane, structure-of-arrays f[q][ir][jt] so that a wavefront of
+// 64 consecutive theta cells reads 64 contiguous values per velocity plane.
+// The collision is evaluated in the Cartesian frame: f^eq depends on v.u and
+// |u|^2 only, which are the same in polar and Cartesian components, so the
+// 33 velocities are compile-time constants (speeds 0, 1.5, 3.5, 7.5, 12.5 of
+// Sec. II.B, directions i*pi/4 fixed in the Cartesian frame).  Polar
+// components are needed only for the Courant numbers and for u_r, u_theta.
+#include <math.h>
+
+#include "pdbm_internal.h"
+
+namespace pdbm {
+namespace {
+
+constexpr double SQH = 0.70710678118654752440;  // cos(pi/4) = sin(pi/4)
+
+__device__ __forceinline__ constexpr double speed(int k)
+{
+    return k == 1 ? 1.5 : k == 2 ? 3.5 : k == 3 ? 7.5 : 12.5;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Renumber them so that each XCD walks one contiguous range of
+// tiles: neighbouring rows of the stencil then meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb)
+{
+    const int q = nb / NXCD, r = nb % NXCD;
+    const int x = bid % NXCD, s = bid / NXCD;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
+__device__ __forceinline__ double ipow(double x, int e)
+{
+    double y = 1.0;
+    for (int i = 0; i < e; ++i) y *= x;
+    return y;
+}
+
+// F_k(T), k = 0..4, from the moment-inversion matrix (Horner in T, float64).
+template <typename real>
+__device__ __forceinline__ void weights(const double *A, double T, real F[5])
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double v = T * (A[4 * k] + T * (A[4 * k + 1] + T * (A[4 * k + 2] + T * A[4 * k + 3])));
+        F[k + 1] = (real)v;
+        s += v;
+    }
+    F[0] = (real)(1.0 - 8.0 * s);
+}
+
+// rho, rho*u (Cartesian), and e = sum f |v|^2 / 2 of one cell.
+template <typename real>
+__device__ __forceinline__ void raw_moments(const real f[NQ], real &rho, real &jx, real &jy, real &e)
+{
+    rho = f[0];
+    jx = 0;
+    jy = 0;
+    e = 0;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real *g = f + 1 + 8 * (k - 1);
+        const real v = (real)speed(k);
+        const real ring = ((g[0] + g[4]) + (g[2] + g[6])) + ((g[1] + g[5]) + (g[3] + g[7]));
+        const real a15 = g[1] - g[5], a37 = g[3] - g[7];
+        const real X = (g[0] - g[4]) + (real)SQH * (a15 - a37);
+        const real Y = (g[2] - g[6]) + (real)SQH * (a15 + a37);
+        rho += ring;
+        jx += v * X;
+        jy += v * Y;
+        e += (real)(0.5 * speed(k) * speed(k)) * ring;
+    }
+}
+
+// Coefficients of the f^eq polynomial in z = v.u / T (Sec. II.B):
+// P(z) = (1 - a + a^2/2) + z (1 - a) + z^2 (1 - a)/2 + z^3/6 + z^4/24, a = u^2/(2T)
+template <typename real>
+struct EqPoly {
+    real c0, c1, c2, wx, wy;
+    __device__ __forceinline__ EqPoly(real ux, real uy, real u2, real T)
+    {
+        const real iT = (real)1 / T;
+        const real a = (real)0.5 * u2 * iT;
+        c0 = (real)1 - a + (real)0.5 * a * a;
+        c1 = (real)1 - a;
+        c2 = (real)0.5 * c1;
+        wx = ux * iT;
+        wy = uy * iT;
+    }
+    // projection of direction d (0..3) on u, divided by T; d+4 is its negative
+    __device__ __forceinline__ real w(int d) const
+    {
+        return d == 0 ? wx : d == 1 ? (real)SQH * (wx + wy) : d == 2 ? wy : (real)SQH * (wy - wx);
+    }
+    // P(z) and P(-z) from the even and odd parts
+    __device__ __forceinline__ void eval(real z, real &pp, real &pm) const
+    {
+        const real z2 = z * z;
+        const real ev = c0 + z2 * (c2 + z2 * (real)(1.0 / 24.0));
+        const real od = z * (c1 + z2 * (real)(1.0 / 6.0));
+        pp = ev + od;
+        pm = ev - od;
+    }
+};
+
+template <typename real>
+__device__ __forceinline__ void equilibrium(const double *A, real rho, real ux, real uy, real T, real f[NQ])
+{
+    real F[5];
+    weights(A, (double)T, F);
+    const real u2 = ux * ux + uy * uy;
+    const EqPoly<real> P(ux, uy, u2, T);
+    f[0] = rho * F[0] * P.c0;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real rF = rho * F[k];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            real pp, pm;
+            P.eval((real)speed(k) * P.w(d), pp, pm);
+            f[1 + 8 * (k - 1) + d] = rF * pp;
+            f[1 + 8 * (k - 1) + d + 4] = rF * pm;
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Sums v[0..4] over the workgroup; the result is valid in thread 0.
+__device__ __forceinline__ void block_sum5(double v[5])
+{
+    __shared__ double lds[BLOCK / 64][5];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) v[i] = wave_sum(v[i]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) lds[w][i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            double s = lds[0][i];
+            for (int j = 1; j < BLOCK / 64; ++j) s += lds[j][i];
+            v[i] = s;
+        }
+}
+
+// Per-block partial sums, then the last block to finish adds the partials in
+// a fixed order (deterministic, no floating-point atomics) and writes the
+// record.  Must be reached by every thread of every block.
+__device__ void diag_reduce(const DiagCtl &dc, double v[5], int tile, int nb)
+{
+    __shared__ int last;
+    block_sum5(v);
+    if (threadIdx.x == 0) {
+        double *p = dc.partials + 5 * (size_t)tile;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) p[i] = v[i];
+        __threadfence();
+        const unsigned done = atomicAdd(dc.counter, 1u);
+        last = done == (unsigned)(nb - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += BLOCK)
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            acc[i] += __hip_atomic_load(dc.partials + 5 * (size_t)b + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    block_sum5(acc);
+    if (threadIdx.x == 0) {
+        pdbm_diag r;
+        r.step = dc.step;
+        r.mass = acc[0];
+        r.energy = acc[1];
+        r.chem = acc[2];
+        r.n_nonfinite = (int64_t)acc[3];
+        r.n_nonphys = (int64_t)acc[4];
+        *dc.out = r;
+        __hip_atomic_store(dc.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Contribution of one cell to the drift report.
+__device__ __forceinline__ void diag_cell(double v[5], double rho, double ux, double uy, double T, double e, double lam,
+                                          double w, double Q)
+{
+    const bool finite = isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy) && isfinite(lam);
+    if (!finite) {
+        v[3] += 1.0;
+        return;
+    }
+    if (rho <= 0.0 || T <= 0.0) v[4] += 1.0;
+    v[0] += rho * w;
+    v[1] += e * w;
+    v[2] += rho * Q * (1.0 - lam) * w;
+}
+
+// ------------------------------------------------------------------ step --
+// One time step of one cell per lane: moments, F_k(T), f^eq, BGK + chemical
+// term, Cochran lambda, and the donor-cell fluxes of f and lambda.
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_step(SolveDesc d, DiagCtl dc)
+{
+    const int nb = gridDim.x;
+    const int tile = xcd_tile(blockIdx.x, nb);
+    const int c = tile * BLOCK + threadIdx.x;
+    double red[5] = {0, 0, 0, 0, 0};
+
+    if (c < d.nr * d.nt) {
+        const int ir = c / d.nt;
+        const int jt = c - ir * d.nt;
+        const real *__restrict__ fin = (const real *)d.f_in;
+        real *__restrict__ fout = (real *)d.f_out;
+        const int64_t P = d.plane;
+        const int64_t idx = (int64_t)ir * d.pitch + jt;
+
+        real f[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) f[q] = fin[q * P + idx];
+
+        // (1) moments
+        real rho, jx, jy, e;
+        raw_moments(f, rho, jx, jy, e);
+        const real irho = (real)1 / rho;
+        const real ux = jx * irho, uy = jy * irho;
+        const real u2 = ux * ux + uy * uy;
+        const real T = e * irho - (real)0.5 * u2;
+        const double Td = (double)T;
+
+        // (2) weights and f^eq polynomial
+        real F[5];
+        weights(d.A, Td, F);
+        const EqPoly<real> EP(ux, uy, u2, T);
+
+        // (3) Cochran rate, gated by the ignition temperature (float64)
+        const double lam = d.lam_in[idx];
+        double a = 0.0, b = 0.0, R = 0.0;
+        const bool on = d.reacts && Td > d.T_th;
+        if (on) {
+            const double p = (double)rho * Td;
+            a = d.w1 * ipow(p, d.m);
+            b = d.w2 * ipow(p, d.n);
+            R = (1.0 - lam) * (a + b * lam);
+        }
+        // M dt = f^eq * beta * (|v-u|^2 - 2T), beta = Q R dt / (2 T^2) (D = 2)
+        const real beta = (real)(d.Q * R * d.dt / (2.0 * Td * Td));
+        const real omega = (real)d.omega;
+        const real keep = (real)1 - omega;
+        const real Bz = (real)-2 * beta * T;
+
+        // geometry: polar components of the 4 direction pairs at theta_j
+        const double2 cs = d.cs[jt];
+        const real cth = (real)cs.x, sth = (real)cs.y;
+        const double ri = d.r_min + ((double)ir + 0.5) * d.dr;
+        const real kr = (real)d.dt_dr, kt = (real)(d.dt_dth / ri);
+        const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+        const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)-SQH * (sth + cth)};
+
+        // neighbour offsets within a plane; ghost rules of Sec. II.D
+        const int64_t rp = ir > 0 ? idx - d.pitch : idx;           // zero gradient / disc
+        const int64_t rn = ir < d.nr - 1 ? idx + d.pitch : idx;    // zero gradient
+        const bool disc0 = d.disc && ir == 0;                       // f(-1,k,i) = f(0,k,(i+4)%8)
+        const int64_t tp = jt > 0 ? idx - 1 : idx + (d.nt - 1);    // periodic
+        const int64_t tn = jt < d.nt - 1 ? idx + 1 : idx - (d.nt - 1);
+        const int rotp = jt > 0 ? 0 : d.sector;                     // sector halo rotation
+        const int rotn = jt < d.nt - 1 ? 0 : 8 - d.sector;
+
+        // rest particle: no streaming
+        fout[idx] = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * f[0];
+
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            const real v = (real)speed(k);
+            const real rF = rho * F[k];
+            const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
+            const int base = 1 + 8 * (k - 1);
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd) {
+                const real z = v * EP.w(dd);
+                real pp, pm;
+                EP.eval(z, pp, pm);
+                const real bz = Bz * z;
+#pragma unroll
+                for (int sgn = 0; sgn < 2; ++sgn) {
+                    const int dir = dd + 4 * sgn;
+                    const int q = base + dir;
+                    const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * f[q] : rF * pm * (Ak - bz) + omega * f[q];
+                    // upwind side: C >= 0 takes the lower neighbour
+                    const real cr = sgn == 0 ? crv[dd] : -crv[dd];
+                    const real ct = sgn == 0 ? ctv[dd] : -ctv[dd];
+                    int64_t ro, to;
+                    int rq, tq;
+                    if (cr >= (real)0) {
+                        ro = rp;
+                        rq = disc0 ? base + ((dir + 4) & 7) : q;
+                    } else {
+                        ro = rn;
+                        rq = q;
+                    }
+                    if (ct >= (real)0) {
+                        to = tp;
+                        tq = base + ((dir + rotp) & 7);
+                    } else {
+                        to = tn;
+                        tq = base + ((dir + rotn) & 7);
+                    }
+                    const real nr_ = fin[rq * P + ro];
+                    const real nt_ = fin[tq * P + to];
+                    const real fc = f[q];
+                    fout[q * P + idx] = coll - v * (fabs(cr) * kr * (fc - nr_) + fabs(ct) * kt * (fc - nt_));
+                }
+            }
+        }
+
+        // (4) lambda: closed-form Cochran step, then upwind by own-cell u
+        const double uxd = (double)ux, uyd = (double)uy;
+        const double urp = uxd * cs.x + uyd * cs.y;
+        const double utp = -uxd * cs.y + uyd * cs.x;
+        double lreac = lam;
+        if (on && a + b > 0.0) {
+            const double q1 = (1.0 - lam) * exp(-(a + b) * d.dt);
+            lreac = 1.0 - (a + b) * q1 / ((a + b * lam) + b * q1);
+        }
+        const double lr = d.lam_in[urp >= 0.0 ? rp : rn];
+        const double lt = d.lam_in[utp >= 0.0 ? tp : tn];
+        d.lam_out[idx] = lreac - fabs(urp) * d.dt_dr * (lam - lr) - fabs(utp) * (d.dt_dth / ri) * (lam - lt);
+
+        if (dc.enabled) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lam, ri * d.dr * d.dth, d.Q);
+    }
+    if (dc.enabled) diag_reduce(dc, red, tile, nb);
+}
+
+// -------------------------------------------------------------- moments --
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_moments(SolveDesc d, double *out, DiagCtl dc)
+{
+    const int nb = gridDim.x;
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    const int ncell = d.nr * d.nt;
+    double red[5] = {0, 0, 0, 0, 0};
+    if (c < ncell) {
+        const int ir = c / d.nt;
+        const int jt = c - ir * d.nt;
+        const real *fin = (const real *)d.f_in;
+        const int64_t idx = (int64_t)ir * d.pitch + jt;
+        real f[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) f[q] = fin[q * d.plane + idx];
+        real rho, jx, jy, e;
+        raw_moments(f, rho, jx, jy, e);
+        const double rd = (double)rho;
+        const double ux = (double)(jx / rho), uy = (double)(jy / rho);
+        const double T = (double)(e / rho - (real)0.5 * ((jx / rho) * (jx / rho) + (jy / rho) * (jy / rho)));
+        const double2 cs = d.cs[jt];
+        const double lam = d.lam_in[idx];
+        if (out) {
+            out[c] = rd;
+            out[(size_t)ncell + c] = ux * cs.x + uy * cs.y;
+            out[2 * (size_t)ncell + c] = -ux * cs.y + uy * cs.x;
+            out[3 * (size_t)ncell + c] = T;
+            out[4 * (size_t)ncell + c] = rd * T;
+            out[5 * (size_t)ncell + c] = lam;
+        }
+        const double ri = d.r_min + ((double)ir + 0.5) * d.dr;
+        diag_cell(red, rd, ux, uy, T, (double)e, lam, ri * d.dr * d.dth, d.Q);
+    }
+    diag_reduce(dc, red, blockIdx.x, nb);
+}
+
+// ------------------------------------------------------------ initial state
+// Pressure with noise, rounded exactly as written (no contraction): the
+// same bits as any IEEE implementation of the formula.
+__device__ __attribute__((noinline)) double noisy_pressure(double rho, double T, double amp, uint64_t h)
+{
+#pragma clang fp contract(off)
+    const double U = (double)(h >> 11) * 0x1.0p-53;
+    const double p = rho * T;
+    return p + amp * (2.0 * U - 1.0);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename real>
+__device__ __forceinline__ void store_eq(const SolveDesc &d, int64_t idx, int jt, double rho, double T, double ur,
+                                         double ut)
+{
+    const double2 cs = d.cs[jt];
+    const double ux = ur * cs.x - ut * cs.y, uy = ur * cs.y + ut * cs.x;
+    real f[NQ];
+    equilibrium<real>(d.A, (real)rho, (real)ux, (real)uy, (real)T, f);
+    real *fo = (real *)d.f_out;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) fo[q * d.plane + idx] = f[q];
+}
+
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_init_ic(SolveDesc d, pdbm_ic ic)
+{
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= d.nr * d.nt) return;
+    const int ir = c / d.nt;
+    const int jt = c - ir * d.nt;
+    const int64_t idx = (int64_t)ir * d.pitch + jt;
+    const double ri = d.r_min + ((double)ir + 0.5) * d.dr;
+    const double *st = ri < ic.r_split ? ic.inner : ic.outer;
+    const uint64_t h = splitmix64(ic.seed ^ ((uint64_t)c * 0x9E3779B97F4A7C15ull));
+    const double p = noisy_pressure(st[0], st[1], ic.p_noise, h);
+    store_eq<real>(d, idx, jt, st[0], p / st[0], st[2], st[3]);
+    d.lam_out[idx] = st[4];
+}
+
+// fields: [5][nr][ntheta] = rho, T, u_r, u_theta, lambda
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_init_fields(SolveDesc d, const double *fields)
+{
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    const int ncell = d.nr * d.nt;
+    if (c >= ncell) return;
+    const int ir = c / d.nt;
+    const int jt = c - ir * d.nt;
+    const int64_t idx = (int64_t)ir * d.pitch + jt;
+    store_eq<real>(d, idx, jt, fields[c], fields[(size_t)ncell + c], fields[2 * (size_t)ncell + c],
+                   fields[3 * (size_t)ncell + c]);
+    d.lam_out[idx] = fields[4 * (size_t)ncell + c];
+}
+
+}  // namespace
+
+int cell_blocks(const SolveDesc &d) { return (int)(((int64_t)d.nr * d.nt + BLOCK - 1) / BLOCK); }
+
+hipError_t launch_step(const SolveDesc &d, bool fp32, const DiagCtl &dc, hipStream_t st)
+{
+    const int nb = cell_blocks(d);
+    if (fp32)
+        hipLaunchKernelGGL(k_step<float>, dim3(nb), dim3(BLOCK), 0, st, d, dc);
+    else
+        hipLaunchKernelGGL(k_step<double>, dim3(nb), dim3(BLOCK), 0, st, d, dc);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const SolveDesc &d, bool fp32, double *out, const DiagCtl &dc, hipStream_t st)
+{
+    const int nb = cell_blocks(d);
+    if (fp32)
+        hipLaunchKernelGGL(k_moments<float>, dim3(nb), dim3(BLOCK), 0, st, d, out, dc);
+    else
+        hipLaunchKernelGGL(k_moments<double>, dim3(nb), dim3(BLOCK), 0, st, d, out, dc);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_ic(const SolveDesc &d, bool fp32, const pdbm_ic &ic, hipStream_t st)
+{
+    const int nb = cell_blocks(d);
+    if (fp32)
+        hipLaunchKernelGGL(k_init_ic<float>, dim3(nb), dim3(BLOCK), 0, st, d, ic);
+    else
+        hipLaunchKernelGGL(k_init_ic<double>, dim3(nb), dim3(BLOCK), 0, st, d, ic);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_fields(const SolveDesc &d, bool fp32, const double *fields, hipStream_t st)
+{
+    const int nb = cell_blocks(d);
+    if (fp32)
+        hipLaunchKernelGGL(k_init_fields<float>, dim3(nb), dim3(BLOCK), 0, st, d, fields);
+    else
+        hipLaunchKernelGGL(k_init_fields<double>, dim3(nb), dim3(BLOCK), 0, st, d, fields);
+    return hipGetLastError();
+}
+
+}  // namespace pdbm

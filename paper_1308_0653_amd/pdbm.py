@@ -1,0 +1,256 @@
+"""ctypes binding of libpdbm (include/pdbm.h): argument marshalling only.
+
+Every function keeps its C name.  All numerical work runs in the HIP kernels
+of libpdbm.so; this module never computes a step itself and raises if the
+library is missing or has no gfx950 device to run on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LIB_PATH = _build.LIB
+
+PDBM_OK, PDBM_EINVAL, PDBM_ECFL, PDBM_ENOMEM, PDBM_EHIP = 0, -1, -2, -3, -4
+PDBM_EAGAIN, PDBM_ENOENT, PDBM_ENONPHYS, PDBM_ENOSYS = -5, -6, -7, -8
+PDBM_FP64, PDBM_FP32 = 0, 1
+PDBM_QUEUED, PDBM_RUNNING, PDBM_DONE, PDBM_FAILED = 0, 1, 2, 3
+PDBM_ALLOW_CFL = 1
+NQ = 33
+
+
+class pdbm_params(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("ntheta", C.c_int32), ("sector", C.c_int32),
+                ("precision", C.c_int32), ("m", C.c_int32), ("n", C.c_int32),
+                ("diag_every", C.c_int32), ("flags", C.c_int32),
+                ("r_min", C.c_double), ("r_max", C.c_double), ("dt", C.c_double),
+                ("tau", C.c_double), ("w1", C.c_double), ("w2", C.c_double),
+                ("Q", C.c_double), ("T_th", C.c_double)]
+
+
+class pdbm_ic(C.Structure):
+    _fields_ = [("r_split", C.c_double), ("inner", C.c_double * 5), ("outer", C.c_double * 5),
+                ("p_noise", C.c_double), ("seed", C.c_uint64)]
+
+
+class pdbm_diag(C.Structure):
+    _fields_ = [("step", C.c_int64), ("mass", C.c_double), ("energy", C.c_double),
+                ("chem", C.c_double), ("n_nonfinite", C.c_int64), ("n_nonphys", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PdbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads libpdbm.so (building it first only if it does not exist)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            _build.build()
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        sig = {
+            "pdbm_strerror": (C.c_char_p, [C.c_int]),
+            "pdbm_last_error": (C.c_char_p, []),
+            "pdbm_version": (C.c_int, []),
+            "pdbm_validate": (C.c_int, [C.POINTER(pdbm_params), C.POINTER(pdbm_ic), dp]),
+            "pdbm_state_bytes": (C.c_int, [C.POINTER(pdbm_params), C.POINTER(C.c_size_t)]),
+            "pdbm_fk_matrix": (C.c_int, [dp]),
+            "pdbm_create": (C.c_int, [C.POINTER(pdbm_params), C.POINTER(pdbm_ic), vp, C.c_size_t, vp,
+                                      C.POINTER(vp)]),
+            "pdbm_destroy": (None, [vp]),
+            "pdbm_set_fields": (C.c_int, [vp, dp]),
+            "pdbm_step": (C.c_int, [vp, C.c_int64]),
+            "pdbm_step_count": (C.c_int64, [vp]),
+            "pdbm_moments": (C.c_int, [vp, dp, C.POINTER(pdbm_diag)]),
+            "pdbm_moments_async": (C.c_int, [vp, vp]),
+            "pdbm_diag_history": (C.c_int, [vp, C.POINTER(pdbm_diag), C.c_int32, C.POINTER(C.c_int32)]),
+            "pdbm_read_f": (C.c_int, [vp, dp, dp]),
+            "pdbm_write_f": (C.c_int, [vp, dp, dp, C.c_int64]),
+            "pdbm_get_state": (C.c_int, [vp, vp, C.POINTER(C.c_size_t)]),
+            "pdbm_set_state": (C.c_int, [vp, vp, C.c_size_t]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc != PDBM_OK:
+        L = lib()
+        raise PdbmError(rc, f"{L.pdbm_strerror(rc).decode()}: {L.pdbm_last_error().decode()}")
+    return rc
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(nr, ntheta, r_min, r_max, dt, tau, w1=0.0, w2=0.0, m=1, n=1, Q=1.0, T_th=1.1,
+                sector=8, precision=PDBM_FP64, diag_every=0, flags=0) -> pdbm_params:
+    return pdbm_params(int(nr), int(ntheta), int(sector), int(precision), int(m), int(n), int(diag_every),
+                       int(flags), float(r_min), float(r_max), float(dt), float(tau), float(w1), float(w2),
+                       float(Q), float(T_th))
+
+
+def make_ic(r_split, inner, outer, p_noise=0.0, seed=0) -> pdbm_ic:
+    return pdbm_ic(float(r_split), (C.c_double * 5)(*map(float, inner)), (C.c_double * 5)(*map(float, outer)),
+                   float(p_noise), int(seed) & 0xFFFFFFFFFFFFFFFF)
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        return 0
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+# ------------------------------------------------------------ C names ----
+
+def pdbm_validate(params: pdbm_params, ic: pdbm_ic | None = None) -> float:
+    cfl = C.c_double(0.0)
+    _check(lib().pdbm_validate(C.byref(params), C.byref(ic) if ic is not None else None, C.byref(cfl)))
+    return cfl.value
+
+
+def pdbm_state_bytes(params: pdbm_params) -> int:
+    n = C.c_size_t(0)
+    _check(lib().pdbm_state_bytes(C.byref(params), C.byref(n)))
+    return n.value
+
+
+def pdbm_fk_matrix() -> np.ndarray:
+    A = np.zeros(16)
+    _check(lib().pdbm_fk_matrix(_dptr(A)))
+    return A.reshape(4, 4)
+
+
+def pdbm_create(params: pdbm_params, ic: pdbm_ic | None = None, workspace=None, stream=None) -> "Solver":
+    return Solver(params, ic, workspace=workspace, stream=stream)
+
+
+class Solver:
+    """Handle of one solve; methods are the pdbm_* calls on it."""
+
+    def __init__(self, params: pdbm_params, ic: pdbm_ic | None = None, workspace=None, stream=None):
+        self.L = lib()
+        self.params = params
+        self.nr, self.nt = params.nr, params.ntheta
+        self.h = C.c_void_p()
+        ws_ptr, ws_bytes = None, 0
+        self._ws = workspace  # keep the caller's buffer (e.g. a torch tensor) alive
+        if workspace is not None:
+            ws_ptr = C.c_void_p(int(workspace.data_ptr()))
+            ws_bytes = workspace.numel() * workspace.element_size()
+        self.stream = _stream_handle(stream)
+        _check(self.L.pdbm_create(C.byref(params), C.byref(ic) if ic is not None else None, ws_ptr, ws_bytes,
+                                  C.c_void_p(self.stream), C.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            self.L.pdbm_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def pdbm_step(self, nsteps: int = 1):
+        _check(self.L.pdbm_step(self.h, int(nsteps)))
+
+    step = pdbm_step
+
+    @property
+    def step_count(self) -> int:
+        return self.L.pdbm_step_count(self.h)
+
+    def pdbm_set_fields(self, fields: np.ndarray):
+        a = np.ascontiguousarray(fields, dtype=np.float64)
+        assert a.shape == (5, self.nr, self.nt)
+        _check(self.L.pdbm_set_fields(self.h, _dptr(a)))
+
+    set_fields = pdbm_set_fields
+
+    def pdbm_moments(self, check: bool = True):
+        """Returns (fields [6][nr][ntheta] = rho, u_r, u_theta, T, p, lambda;
+        drift report dict)."""
+        out = np.empty((6, self.nr, self.nt))
+        d = pdbm_diag()
+        rc = self.L.pdbm_moments(self.h, _dptr(out), C.byref(d))
+        if rc != PDBM_ENONPHYS or check:
+            _check(rc)
+        return out, d.as_dict()
+
+    moments = pdbm_moments
+
+    def pdbm_moments_async(self, out_tensor):
+        """Enqueues the fields into a caller-owned float64 device tensor of
+        shape [6][nr][ntheta]."""
+        assert out_tensor.is_cuda and out_tensor.is_contiguous() and out_tensor.numel() == 6 * self.nr * self.nt
+        _check(self.L.pdbm_moments_async(self.h, C.c_void_p(int(out_tensor.data_ptr()))))
+
+    moments_async = pdbm_moments_async
+
+    def pdbm_diag_history(self, cap: int = 4096):
+        buf = (pdbm_diag * cap)()
+        n = C.c_int32(0)
+        _check(self.L.pdbm_diag_history(self.h, buf, cap, C.byref(n)))
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    diag_history = pdbm_diag_history
+
+    def pdbm_read_f(self):
+        f = np.empty((NQ, self.nr, self.nt))
+        lam = np.empty((self.nr, self.nt))
+        _check(self.L.pdbm_read_f(self.h, _dptr(f), _dptr(lam)))
+        return f, lam
+
+    read_f = pdbm_read_f
+
+    def pdbm_write_f(self, f: np.ndarray, lam: np.ndarray, step: int = 0):
+        fa = np.ascontiguousarray(f, dtype=np.float64)
+        la = np.ascontiguousarray(lam, dtype=np.float64)
+        assert fa.shape == (NQ, self.nr, self.nt) and la.shape == (self.nr, self.nt)
+        _check(self.L.pdbm_write_f(self.h, _dptr(fa), _dptr(la), int(step)))
+
+    write_f = pdbm_write_f
+
+    def pdbm_get_state(self) -> bytes:
+        n = C.c_size_t(0)
+        _check(self.L.pdbm_get_state(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(self.L.pdbm_get_state(self.h, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    get_state = pdbm_get_state
+
+    def pdbm_set_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(self.L.pdbm_set_state(self.h, buf, len(blob)))
+
+    set_state = pdbm_set_state

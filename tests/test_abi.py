@@ -1,0 +1,144 @@
+"""Host-side checks of libpdbm that need no GPU: the library loads and
+exports every entry point the header declares, parameter validation, the
+Courant bound, and the moment-inversion matrix."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_0653_amd import pdbm as P
+from paper_1308_0653_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(pdbm_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(P.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for name in syms:
+        assert hasattr(L, name), name
+
+
+def _good():
+    w = W.small_fp64()
+    return P.make_params(**w.params_kw())
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nr", 0), ("ntheta", 0), ("sector", 0), ("sector", 9), ("precision", 2), ("m", -1), ("n", 65),
+    ("diag_every", -1), ("flags", 4), ("r_min", -0.1), ("r_max", 0.1), ("r_max", math.nan), ("dt", 0.0),
+    ("dt", -1e-5), ("dt", math.inf), ("tau", 0.0), ("tau", math.nan), ("w1", -1.0), ("w2", math.inf),
+    ("Q", -0.5), ("T_th", math.nan)])
+def test_validate_rejects_bad_parameters(field, value):
+    p = _good()
+    setattr(p, field, value)
+    with pytest.raises(P.PdbmError) as e:
+        P.pdbm_validate(p)
+    assert e.value.code == P.PDBM_EINVAL
+
+
+@pytest.mark.parametrize("which,idx,value", [("inner", 0, 0.0), ("outer", 1, -1.0), ("inner", 4, math.nan),
+                                             ("noise", 0, -1e-6), ("noise", 0, 5.0)])
+def test_validate_rejects_bad_initial_state(which, idx, value):
+    w = W.small_fp64()
+    kw = w.ic_kw()
+    if which == "noise":
+        kw["p_noise"] = value
+    else:
+        t = list(kw[which])
+        t[idx] = value
+        kw[which] = tuple(t)
+    with pytest.raises(P.PdbmError) as e:
+        P.pdbm_validate(_good(), P.make_ic(**kw))
+    assert e.value.code == P.PDBM_EINVAL
+
+
+def _courant_bruteforce(nr, nt, r0, r1, dt, sector=8):
+    """Largest |C_r| + |C_theta| of the fastest speed over every cell and
+    direction, straight from the Courant-number definitions (Sec. II.C)."""
+    dr, dth = (r1 - r0) / nr, sector * np.pi / 4 / nt
+    r = r0 + (np.arange(nr) + 0.5) * dr
+    th = (np.arange(nt) + 0.5) * dth
+    worst = 0.0
+    for i in range(8):
+        a = i * np.pi / 4 - th[None, :]
+        c = 12.5 * dt * (np.abs(np.cos(a)) / dr + np.abs(np.sin(a)) / (r[:, None] * dth))
+        worst = max(worst, c.max())
+    return worst
+
+
+@pytest.mark.parametrize("wl", [W.small_fp64(), W.outward_fp64()] + W.batch_sweep(count=6))
+def test_courant_bound_of_workloads(wl):
+    p = P.make_params(**wl.params_kw())
+    cfl = P.pdbm_validate(p, P.make_ic(**wl.ic_kw()))
+    ref = _courant_bruteforce(wl.nr, wl.ntheta, wl.r_min, wl.r_max, wl.dt)
+    assert abs(cfl - ref) < 1e-12 * ref
+    assert cfl < 1.0
+
+
+def test_cfl_violation_is_rejected_unless_allowed():
+    p = _good()
+    p.dt = 1e-3
+    with pytest.raises(P.PdbmError) as e:
+        P.pdbm_validate(p)
+    assert e.value.code == P.PDBM_ECFL
+    p.flags = P.PDBM_ALLOW_CFL
+    assert P.pdbm_validate(p) > 1.0
+
+
+@pytest.mark.parametrize("T", [0.3, 1.0, 2.4, 7.7, 13.3, 50.0])
+def test_fk_matrix_reproduces_weights(T):
+    """The library's inverted moment system gives the same F_k(T) as the
+    oracle's printed closed form (Sec. II.B)."""
+    A = P.pdbm_fk_matrix()
+    F = [T * (A[k, 0] + T * (A[k, 1] + T * (A[k, 2] + T * A[k, 3]))) for k in range(4)]
+    ref = O.weights(T)[1:]
+    for a, b in zip(F, ref):
+        assert abs(a - b) <= 1e-13 * abs(b)
+    # and the moment constraints themselves
+    v = [1.5, 3.5, 7.5, 12.5]
+    for n in range(1, 5):
+        lhs = sum(8 * F[k] * v[k] ** (2 * n) for k in range(4))
+        assert abs(lhs - 2 ** n * math.factorial(n) * T ** n) <= 1e-12 * T ** n * 2 ** n * math.factorial(n)
+
+
+def test_state_bytes_cover_both_buffers():
+    w = W.outward_fp64()
+    p = P.make_params(**w.params_kw())
+    b64 = P.pdbm_state_bytes(p)
+    assert b64 >= 2 * 33 * 1024 * 1024 * 8 + 2 * 1024 * 1024 * 8
+    p.precision = P.PDBM_FP32
+    b32 = P.pdbm_state_bytes(p)
+    assert 2 * 33 * 1024 * 1024 * 4 + 2 * 1024 * 1024 * 8 <= b32 < b64
+    assert b32 / (1024 * 1024) < 300  # 280 B per cell plus small tables
+
+
+def test_error_strings():
+    L = P.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+        assert len(L.pdbm_strerror(code)) > 0
+    assert L.pdbm_version() >= 1
+
+
+def test_create_without_gpu_fails_loudly():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(P.PdbmError) as e:
+        P.Solver(_good(), P.make_ic(**W.small_fp64().ic_kw()))
+    assert e.value.code in (P.PDBM_ENOSYS, P.PDBM_EHIP)
