@@ -61,7 +61,7 @@ enum { PDBM_QUEUED = 0, PDBM_RUNNING = 1, PDBM_DONE = 2, PDBM_FAILED = 3 }; /* r
 enum { PDBM_ALLOW_CFL = 1 };                                   /* flags       */
 
 /* Problem statement of one solve (Sec. II.D and III of the paper).
- *   nr, ntheta   cells in r and theta (nr >= 2, ntheta >= 1)
+ *   nr, ntheta   cells in r and theta (>= 1, nr * ntheta <= 2^24)
  *   sector       azimuthal extent s*pi/4, s in 1..8 (8 = full annulus).  The
  *                periodic theta halo rotates the direction index by s:
  *                f_{k,i}(j=-1) = f_{k,(i+s)%8}(ntheta-1),

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -30,7 +31,7 @@ int fail(int code, const std::string &msg)
     } while (0)
 
 constexpr double SPEEDS[5] = {0.0, 1.5, 3.5, 7.5, 12.5};  // Sec. II.B
-constexpr int64_t MAX_CELLS = int64_t(1) << 27;
+constexpr int64_t MAX_CELLS = int64_t(1) << 24;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -43,13 +44,22 @@ struct Layout {
     size_t esz;
 };
 
+int blocks_of(const pdbm_params &p)
+{
+    const int64_t cellb = ((int64_t)p.nr * p.ntheta + BLOCK - 1) / BLOCK;
+    const int rows = rows_per_wave(p.nr, p.ntheta);
+    const int64_t waves = (int64_t)((p.nr + rows - 1) / rows) * ((p.ntheta + STRIP - 1) / STRIP);
+    const int64_t stepb = (waves + BLOCK / 64 - 1) / (BLOCK / 64);
+    return (int)(cellb > stepb ? cellb : stepb);
+}
+
 Layout layout_of(const pdbm_params &p)
 {
     Layout L;
     L.esz = p.precision == PDBM_FP32 ? sizeof(float) : sizeof(double);
     L.pitch = pitch_of(p.ntheta);
     const size_t cells_p = (size_t)p.nr * L.pitch;
-    L.nblocks = (int)(((int64_t)p.nr * p.ntheta + BLOCK - 1) / BLOCK);
+    L.nblocks = blocks_of(p);
     L.f = align256((size_t)NQ * cells_p * L.esz);
     L.lam = align256(cells_p * sizeof(double));
     L.cs = align256((size_t)p.ntheta * sizeof(double2));
@@ -63,6 +73,23 @@ Layout layout_of(const pdbm_params &p)
 bool is_fin(double x) { return std::isfinite(x); }
 
 }  // namespace
+
+// Rows per wavefront: enough wavefronts to fill the chip about twice over at
+// two per SIMD, but at least 2 rows so the two bounding rows stay a minor
+// share of the loads.  PDBM_ROWS_PER_WAVE overrides it (tuning).
+int pdbm::rows_per_wave(int nr, int nt)
+{
+    static const int env = [] {
+        const char *e = std::getenv("PDBM_ROWS_PER_WAVE");
+        return e ? std::atoi(e) : 0;
+    }();
+    if (env > 0) return env;
+    const int64_t strips = (nt + STRIP - 1) / STRIP;
+    int64_t rows = (int64_t)nr * strips / 4096;
+    if (rows < 2) rows = 2;
+    if (rows > 64) rows = 64;
+    return (int)rows;
+}
 
 // Largest |C_r| + |C_theta| over the grid for the fastest speed: the
 // innermost row has the largest azimuthal Courant number.
@@ -110,7 +137,7 @@ int pdbm_validate(const pdbm_params *p, const pdbm_ic *ic, double *cfl)
 {
     if (!p) return fail(PDBM_EINVAL, "params is NULL");
     if (p->nr < 1 || p->ntheta < 1) return fail(PDBM_EINVAL, "nr and ntheta must be >= 1");
-    if ((int64_t)p->nr * p->ntheta > MAX_CELLS) return fail(PDBM_EINVAL, "grid larger than 2^27 cells");
+    if ((int64_t)p->nr * p->ntheta > MAX_CELLS) return fail(PDBM_EINVAL, "grid larger than 2^24 cells");
     if (p->sector < 1 || p->sector > 8) return fail(PDBM_EINVAL, "sector must be in 1..8");
     if (p->precision != PDBM_FP64 && p->precision != PDBM_FP32) return fail(PDBM_EINVAL, "unknown precision");
     if (p->m < 0 || p->n < 0 || p->m > 64 || p->n > 64) return fail(PDBM_EINVAL, "m, n must be in 0..64");
@@ -216,6 +243,7 @@ struct pdbm_solver {
         d.n = p.n;
         d.disc = p.r_min == 0.0;
         d.reacts = (p.w1 > 0.0 || p.w2 > 0.0) ? 1 : 0;
+        d.rows = rows_per_wave(p.nr, p.ntheta);
         d.plane = (int64_t)p.nr * L.pitch;
         d.dr = (p.r_max - p.r_min) / p.nr;
         d.dth = p.sector * M_PI / 4.0 / p.ntheta;

@@ -13,6 +13,7 @@ constexpr int NQ = 33;          // D2V33: rest particle + 4 speeds x 8 direction
 constexpr int BLOCK = 256;      // threads per workgroup of the cell kernels
 constexpr int HIST_CAP = 4096;  // drift reports kept per solve
 constexpr int NXCD = 8;         // accelerator complex dies of an MI355X
+constexpr int STRIP = 62;       // theta columns stored per wavefront (64 lanes minus 2 halo lanes)
 
 // Everything a kernel needs to know about one solve.  Passed by value as a
 // kernel argument (one solve per launch) or read from a device table (packed
@@ -25,6 +26,7 @@ struct SolveDesc {
     const double2 *cs;  // [ntheta] (cos theta_j, sin theta_j)
     int32_t nr, nt, pitch, sector;
     int32_t m, n, disc, reacts;  // disc: r_min == 0; reacts: w1+w2 > 0
+    int32_t rows, pad_;          // rows marched by one wavefront per step
     int64_t plane;               // nr * pitch, elements per velocity plane
     double r_min, dr, dth;
     double dt_dr, dt_dth;  // dt/dr, dt/dtheta
@@ -50,5 +52,8 @@ hipError_t launch_init_ic(const SolveDesc &d, bool fp32, const pdbm_ic &ic, hipS
 hipError_t launch_init_fields(const SolveDesc &d, bool fp32, const double *fields, hipStream_t st);
 hipError_t launch_moments(const SolveDesc &d, bool fp32, double *out, const DiagCtl &dc, hipStream_t st);
 int cell_blocks(const SolveDesc &d);
+int step_blocks(const SolveDesc &d);
+// Rows per wavefront of the step kernel for an nr x nt grid.
+int rows_per_wave(int nr, int nt);
 
 }  // namespace pdbm

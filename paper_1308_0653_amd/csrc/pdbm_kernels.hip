@@ -208,138 +208,243 @@ __device__ __forceinline__ void diag_cell(double v[5], double rho, double ux, do
 }
 
 // ------------------------------------------------------------------ step --
-// One time step of one cell per lane: moments, F_k(T), f^eq, BGK + chemical
-// term, Cochran lambda, and the donor-cell fluxes of f and lambda.
-template <typename real>
-__global__ __launch_bounds__(BLOCK) void k_step(SolveDesc d, DiagCtl dc)
+// Cross-lane moves within a wavefront (DPP wave shifts): the value held by
+// lane-1 (from_left) and by lane+1 (from_right).  Lanes 0 / 63 receive 0; they
+// are halo lanes whose results are never stored.
+__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
+__device__ __forceinline__ double from_left(double v)
 {
-    const int nb = gridDim.x;
-    const int tile = xcd_tile(blockIdx.x, nb);
-    const int c = tile * BLOCK + threadIdx.x;
-    double red[5] = {0, 0, 0, 0, 0};
+    return __hiloint2double(dpp_shr1(__double2hiint(v)), dpp_shr1(__double2loint(v)));
+}
+__device__ __forceinline__ double from_right(double v)
+{
+    return __hiloint2double(dpp_shl1(__double2hiint(v)), dpp_shl1(__double2loint(v)));
+}
 
-    if (c < d.nr * d.nt) {
-        const int ir = c / d.nt;
-        const int jt = c - ir * d.nt;
-        const real *__restrict__ fin = (const real *)d.f_in;
-        real *__restrict__ fout = (real *)d.f_out;
-        const int64_t P = d.plane;
-        const int64_t idx = (int64_t)ir * d.pitch + jt;
+// A wavefront owns a strip of STRIP consecutive theta columns plus one halo
+// column on each side (lanes 0 and 63), and marches outward over a block of
+// rows.  Rows i and i+1 of f are held in registers and row i-1 in a
+// lane-private LDS slot: the radial neighbours come from there, the azimuthal
+// ones from the adjacent lanes, so every f value is read from memory once per
+// step (plus the halo columns and the two rows bounding the block).  Row i+1
+// is requested before row i is computed, which keeps one row of loads in
+// flight per wavefront.
+template <typename real, bool ROT>
+struct Strip {
+    const SolveDesc &d;
+    const real *__restrict__ fin;
+    real *__restrict__ fout;
+    int lane, col, pc, rot;  // column, physical column, direction shift of this lane's data
+    bool useful;
 
-        real f[NQ];
+    __device__ __forceinline__ Strip(const SolveDesc &d_, int strip) : d(d_)
+    {
+        fin = (const real *)d.f_in;
+        fout = (real *)d.f_out;
+        lane = threadIdx.x & 63;
+        col = strip * STRIP - 1 + lane;
+        const int wraps = col < 0 ? -1 : col / d.nt;  // periodic images of the sector
+        pc = col - wraps * d.nt;
+        rot = ROT ? ((-wraps * d.sector) & 7) : 0;
+        useful = lane >= 1 && lane <= STRIP && col < d.nt;
+    }
+
+    // plane of direction `dir` of speed ring `base` as seen by this lane
+    __device__ __forceinline__ int plane(int base, int dir) const { return ROT ? base + ((dir + rot) & 7) : base + dir; }
+
+    __device__ __forceinline__ void load_row(int row, real f[NQ], double &lam) const
+    {
+        const int64_t off = (int64_t)row * d.pitch + pc;
+        f[0] = fin[off];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) f[q] = fin[q * P + idx];
+        for (int k = 1; k <= 4; ++k)
+#pragma unroll
+            for (int dir = 0; dir < 8; ++dir) {
+                const int base = 1 + 8 * (k - 1);
+                f[base + dir] = fin[(int64_t)plane(base, dir) * d.plane + off];
+            }
+        lam = d.lam_in[off];
+    }
+};
 
-        // (1) moments
-        real rho, jx, jy, e;
-        raw_moments(f, rho, jx, jy, e);
-        const real irho = (real)1 / rho;
-        const real ux = jx * irho, uy = jy * irho;
-        const real u2 = ux * ux + uy * uy;
-        const real T = e * irho - (real)0.5 * u2;
-        const double Td = (double)T;
+// One row of one strip: moments, F_k(T), f^eq, BGK + chemical term, Cochran
+// lambda, donor-cell fluxes of f and lambda.  prev (LDS, this lane's column):
+// row i-1, replaced by row i as it is consumed; fc, fn: rows i, i+1.
+template <typename real, bool ROT>
+__device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, volatile real (*prev)[64], const real fc[NQ],
+                                           const real fn[NQ], double lp, double lc, double ln, real cth, real sth,
+                                           double csx, double csy, double red[5], bool diag)
+{
+    const SolveDesc &d = S.d;
+    // (1) moments
+    real rho, jx, jy, e;
+    raw_moments(fc, rho, jx, jy, e);
+    const real irho = (real)1 / rho;
+    const real ux = jx * irho, uy = jy * irho;
+    const real u2 = ux * ux + uy * uy;
+    const real T = e * irho - (real)0.5 * u2;
+    const double Td = (double)T;
 
-        // (2) weights and f^eq polynomial
-        real F[5];
-        weights(d.A, Td, F);
-        const EqPoly<real> EP(ux, uy, u2, T);
+    // (2) weights and f^eq polynomial
+    real F[5];
+    weights(d.A, Td, F);
+    const EqPoly<real> EP(ux, uy, u2, T);
 
-        // (3) Cochran rate, gated by the ignition temperature (float64)
-        const double lam = d.lam_in[idx];
-        double a = 0.0, b = 0.0, R = 0.0;
-        const bool on = d.reacts && Td > d.T_th;
-        if (on) {
-            const double p = (double)rho * Td;
-            a = d.w1 * ipow(p, d.m);
-            b = d.w2 * ipow(p, d.n);
-            R = (1.0 - lam) * (a + b * lam);
-        }
-        // M dt = f^eq * beta * (|v-u|^2 - 2T), beta = Q R dt / (2 T^2) (D = 2)
-        const real beta = (real)(d.Q * R * d.dt / (2.0 * Td * Td));
-        const real omega = (real)d.omega;
-        const real keep = (real)1 - omega;
-        const real Bz = (real)-2 * beta * T;
+    // (3) Cochran rate, gated by the ignition temperature (float64)
+    double a = 0.0, b = 0.0, R = 0.0;
+    const bool on = d.reacts && Td > d.T_th;
+    if (on) {
+        const double p = (double)rho * Td;
+        a = d.w1 * ipow(p, d.m);
+        b = d.w2 * ipow(p, d.n);
+        R = (1.0 - lc) * (a + b * lc);
+    }
+    // M dt = f^eq * beta * (|v-u|^2 - 2T), beta = Q R dt / (2 T^2) (D = 2)
+    const real beta = (real)(d.Q * R * d.dt / (2.0 * Td * Td));
+    const real omega = (real)d.omega;
+    const real keep = (real)1 - omega;
+    const real Bz = (real)-2 * beta * T;
 
-        // geometry: polar components of the 4 direction pairs at theta_j
-        const double2 cs = d.cs[jt];
-        const real cth = (real)cs.x, sth = (real)cs.y;
-        const double ri = d.r_min + ((double)ir + 0.5) * d.dr;
-        const real kr = (real)d.dt_dr, kt = (real)(d.dt_dth / ri);
-        const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
-        const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)-SQH * (sth + cth)};
+    // Courant numbers: polar components of directions dd = 0..3 at theta_j,
+    // v_r = v (cos(dd pi/4) cos th + sin(dd pi/4) sin th),
+    // v_theta = v (sin(dd pi/4) cos th - cos(dd pi/4) sin th); dd+4 is the negative
+    const double ri = d.r_min + ((double)ir + 0.5) * d.dr;
+    const real kr = (real)d.dt_dr, kt = (real)(d.dt_dth / ri);
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
 
-        // neighbour offsets within a plane; ghost rules of Sec. II.D
-        const int64_t rp = ir > 0 ? idx - d.pitch : idx;           // zero gradient / disc
-        const int64_t rn = ir < d.nr - 1 ? idx + d.pitch : idx;    // zero gradient
-        const bool disc0 = d.disc && ir == 0;                       // f(-1,k,i) = f(0,k,(i+4)%8)
-        const int64_t tp = jt > 0 ? idx - 1 : idx + (d.nt - 1);    // periodic
-        const int64_t tn = jt < d.nt - 1 ? idx + 1 : idx - (d.nt - 1);
-        const int rotp = jt > 0 ? 0 : d.sector;                     // sector halo rotation
-        const int rotn = jt < d.nt - 1 ? 0 : 8 - d.sector;
+    const bool store = S.useful;
+    const int64_t off = (int64_t)ir * d.pitch + S.pc;
+    real *__restrict__ fout = S.fout;
 
-        // rest particle: no streaming
-        fout[idx] = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * f[0];
+    // rest particle: no streaming
+    if (store) fout[off] = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * fc[0];
+    const int lane = S.lane;
 
 #pragma unroll
-        for (int k = 1; k <= 4; ++k) {
-            const real v = (real)speed(k);
-            const real rF = rho * F[k];
-            const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
-            const int base = 1 + 8 * (k - 1);
+    for (int k = 1; k <= 4; ++k) {
+        const real v = (real)speed(k);
+        const real rF = rho * F[k];
+        const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
+        const int base = 1 + 8 * (k - 1);
 #pragma unroll
-            for (int dd = 0; dd < 4; ++dd) {
-                const real z = v * EP.w(dd);
-                real pp, pm;
-                EP.eval(z, pp, pm);
-                const real bz = Bz * z;
+        for (int dd = 0; dd < 4; ++dd) {
+            const real z = v * EP.w(dd);
+            real pp, pm;
+            EP.eval(z, pp, pm);
+            const real bz = Bz * z;
 #pragma unroll
-                for (int sgn = 0; sgn < 2; ++sgn) {
-                    const int dir = dd + 4 * sgn;
-                    const int q = base + dir;
-                    const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * f[q] : rF * pm * (Ak - bz) + omega * f[q];
-                    // upwind side: C >= 0 takes the lower neighbour
-                    const real cr = sgn == 0 ? crv[dd] : -crv[dd];
-                    const real ct = sgn == 0 ? ctv[dd] : -ctv[dd];
-                    int64_t ro, to;
-                    int rq, tq;
-                    if (cr >= (real)0) {
-                        ro = rp;
-                        rq = disc0 ? base + ((dir + 4) & 7) : q;
-                    } else {
-                        ro = rn;
-                        rq = q;
-                    }
-                    if (ct >= (real)0) {
-                        to = tp;
-                        tq = base + ((dir + rotp) & 7);
-                    } else {
-                        to = tn;
-                        tq = base + ((dir + rotn) & 7);
-                    }
-                    const real nr_ = fin[rq * P + ro];
-                    const real nt_ = fin[tq * P + to];
-                    const real fc = f[q];
-                    fout[q * P + idx] = coll - v * (fabs(cr) * kr * (fc - nr_) + fabs(ct) * kt * (fc - nt_));
-                }
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const int q = base + dd + 4 * sgn;
+                const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * fc[q] : rF * pm * (Ak - bz) + omega * fc[q];
+                // upwind neighbour: C >= 0 takes the lower one (Sec. II.C)
+                const real cr = sgn == 0 ? crv[dd] : -crv[dd];
+                const real ct = sgn == 0 ? ctv[dd] : -ctv[dd];
+                const real below = prev[q][lane];
+                prev[q][lane] = fc[q];
+                const real nbr = cr >= (real)0 ? below : fn[q];
+                const real left = from_left(fc[q]), right = from_right(fc[q]);
+                const real nbt = ct >= (real)0 ? left : right;
+                const real x = fc[q];
+                const real out = coll - v * (fabs(cr) * kr * (x - nbr) + fabs(ct) * kt * (x - nbt));
+                if (store) fout[(int64_t)q * d.plane + off] = out;
             }
         }
-
-        // (4) lambda: closed-form Cochran step, then upwind by own-cell u
-        const double uxd = (double)ux, uyd = (double)uy;
-        const double urp = uxd * cs.x + uyd * cs.y;
-        const double utp = -uxd * cs.y + uyd * cs.x;
-        double lreac = lam;
-        if (on && a + b > 0.0) {
-            const double q1 = (1.0 - lam) * exp(-(a + b) * d.dt);
-            lreac = 1.0 - (a + b) * q1 / ((a + b * lam) + b * q1);
-        }
-        const double lr = d.lam_in[urp >= 0.0 ? rp : rn];
-        const double lt = d.lam_in[utp >= 0.0 ? tp : tn];
-        d.lam_out[idx] = lreac - fabs(urp) * d.dt_dr * (lam - lr) - fabs(utp) * (d.dt_dth / ri) * (lam - lt);
-
-        if (dc.enabled) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lam, ri * d.dr * d.dth, d.Q);
+        // keep the scheduler from interleaving the rings (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
     }
-    if (dc.enabled) diag_reduce(dc, red, tile, nb);
+
+    // (4) lambda: closed-form Cochran step, then upwind by own-cell u
+    const double uxd = (double)ux, uyd = (double)uy;
+    const double urp = uxd * csx + uyd * csy;
+    const double utp = -uxd * csy + uyd * csx;
+    double lreac = lc;
+    if (on && a + b > 0.0) {
+        const double q1 = (1.0 - lc) * exp(-(a + b) * d.dt);
+        lreac = 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
+    }
+    const double lleft = from_left(lc), lright = from_right(lc);
+    const double lr = urp >= 0.0 ? lp : ln;
+    const double lt = utp >= 0.0 ? lleft : lright;
+    if (store) d.lam_out[off] = lreac - fabs(urp) * d.dt_dr * (lc - lr) - fabs(utp) * (d.dt_dth / ri) * (lc - lt);
+
+    if (diag && store) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lc, ri * d.dr * d.dth, d.Q);
+}
+
+// Work of one wavefront: strip `strip`, rows [i0, i1).  prev: this
+// wavefront's [NQ][64] LDS slots.
+template <typename real, bool ROT>
+__device__ __forceinline__ void march(const SolveDesc &d, int strip, int i0, int i1, volatile real (*prev)[64], double red[5],
+                                      bool diag)
+{
+    const Strip<real, ROT> S(d, strip);
+    const int lane = S.lane;
+    const double2 cs = d.cs[S.pc];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    real fc[NQ], fn[NQ];
+    double lp, lc, ln;
+    S.load_row(i0, fc, lc);
+    if (i0 > 0) {
+        S.load_row(i0 - 1, fn, lp);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) prev[q][lane] = fn[q];
+    } else {
+        // ghost row below r_min: zero gradient, or the disc-centre rule
+        // f(-1, j, k, i) = f(0, j, k, (i+4)%8) (Sec. II.D)
+        prev[0][lane] = fc[0];
+#pragma unroll
+        for (int q = 1; q < NQ; ++q) {
+            const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8;
+            prev[q][lane] = d.disc ? fc[base + ((dir + 4) & 7)] : fc[q];
+        }
+        lp = lc;
+    }
+    for (int ir = i0; ir < i1; ++ir) {
+        if (ir + 1 < d.nr) {
+            S.load_row(ir + 1, fn, ln);
+        } else {  // zero-gradient ghost row above r_max
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) fn[q] = fc[q];
+            ln = lc;
+        }
+        update_row<real, ROT>(S, ir, prev, fc, fn, lp, lc, ln, cth, sth, cs.x, cs.y, red, diag);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) fc[q] = fn[q];
+        lp = lc;
+        lc = ln;
+    }
+}
+
+// One time step of a whole solve.  Wave w of the grid takes tile t = (its
+// block's XCD-ordered index) * 4 + w: strip t / nrb, row block t % nrb.
+// Occupancy: float32 rows fit two wavefronts per SIMD; float64 rows take
+// the whole register file of one (the next row in flight is 66 VGPRs).
+template <typename real>
+struct StepOcc {
+    static constexpr int waves = sizeof(real) == 4 ? 2 : 1;
+};
+
+template <typename real, bool ROT>
+__global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(SolveDesc d, DiagCtl dc)
+{
+    const int nb = gridDim.x;
+    const int blk = xcd_tile(blockIdx.x, nb);
+    const int t = blk * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int nrb = (d.nr + d.rows - 1) / d.rows;
+    const int nstrip = (d.nt + STRIP - 1) / STRIP;
+    __shared__ real prev[BLOCK / 64][NQ][64];
+    double red[5] = {0, 0, 0, 0, 0};
+    const bool diag = dc.enabled != 0;
+    if (t < nrb * nstrip) {
+        const int strip = t / nrb, rb = t - strip * nrb;
+        const int i0 = rb * d.rows;
+        const int i1 = min(i0 + d.rows, d.nr);
+        march<real, ROT>(d, strip, i0, i1, prev[threadIdx.x >> 6], red, diag);
+    }
+    if (diag) diag_reduce(dc, red, blk, nb);
 }
 
 // -------------------------------------------------------------- moments --
@@ -446,13 +551,28 @@ __global__ __launch_bounds__(BLOCK) void k_init_fields(SolveDesc d, const double
 
 int cell_blocks(const SolveDesc &d) { return (int)(((int64_t)d.nr * d.nt + BLOCK - 1) / BLOCK); }
 
+int step_blocks(const SolveDesc &d)
+{
+    const int64_t nrb = (d.nr + d.rows - 1) / d.rows;
+    const int64_t nstrip = (d.nt + STRIP - 1) / STRIP;
+    return (int)((nrb * nstrip + BLOCK / 64 - 1) / (BLOCK / 64));
+}
+
 hipError_t launch_step(const SolveDesc &d, bool fp32, const DiagCtl &dc, hipStream_t st)
 {
-    const int nb = cell_blocks(d);
-    if (fp32)
-        hipLaunchKernelGGL(k_step<float>, dim3(nb), dim3(BLOCK), 0, st, d, dc);
-    else
-        hipLaunchKernelGGL(k_step<double>, dim3(nb), dim3(BLOCK), 0, st, d, dc);
+    const int nb = step_blocks(d);
+    const bool rot = d.sector != 8;
+    if (fp32) {
+        if (rot)
+            hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, d, dc);
+        else
+            hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, d, dc);
+    } else {
+        if (rot)
+            hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, d, dc);
+        else
+            hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, d, dc);
+    }
     return hipGetLastError();
 }
 

@@ -58,6 +58,13 @@ def lib():
     """Loads libpdbm.so (building it first only if it does not exist)."""
     global _lib
     if _lib is None:
+        # Bring in torch's HIP runtime first when torch is installed, so that
+        # the process holds one HIP runtime and torch streams and device
+        # memory are valid handles for the library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             _build.build()
         L = C.CDLL(LIB_PATH)

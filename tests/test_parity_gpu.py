@@ -41,8 +41,19 @@ def rel_linf(a, b):
     return np.abs(a - b).max() / (den if den > 0 else 1.0)
 
 
+def field_scales(ref):
+    """Normalisers of the normwise error: each field's max |value|; the two
+    velocity components share one scale, the larger of their maxima and the
+    thermal speed sqrt(max T) (u can be zero up to rounding)."""
+    sc = [np.abs(ref[k]).max() for k in range(6)]
+    us = max(sc[1], sc[2], np.sqrt(np.abs(ref[3]).max()))
+    sc[1] = sc[2] = us
+    return [s if s > 0 else 1.0 for s in sc]
+
+
 def assert_fields_close(got, ref, tol, fields=range(6), label=""):
-    errs = {FIELD_NAMES[k]: rel_linf(got[k], ref[k]) for k in fields}
+    sc = field_scales(ref)
+    errs = {FIELD_NAMES[k]: np.abs(got[k] - ref[k]).max() / sc[k] for k in fields}
     print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     for k, v in errs.items():
         assert v <= tol, (label, k, v)
