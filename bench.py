@@ -34,7 +34,22 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 form")
     ap.add_argument("--cpu-steps", type=int, default=60, help="oracle steps of the CPU sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(torch):
+    """A plain copy of known size: 1 GiB read + 1 GiB written per launch."""
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n, "launches": 5}))
 
 
 def time_solver(P, w, precision, steps, warmup, torch):
@@ -95,6 +110,9 @@ def main():
         print("bench.py needs an MI355X GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.copy_probe:
+        copy_probe(torch)
+        return
     w = W.outward_fp64()
     wall, ev, diag = time_solver(P, w, P.PDBM_FP64, a.steps, a.warmup, torch)
     value = w.cells * a.steps / wall

@@ -39,7 +39,7 @@ int pitch_of(int nt) { return nt <= 16 ? nt : (nt + 31) / 32 * 32; }
 
 // Device memory of one solve, in this order.
 struct Layout {
-    size_t f, lam, cs, partials, counter, hist, total;
+    size_t f, lam, cs, desc, partials, counter, hist, total;
     int pitch, nblocks;
     size_t esz;
 };
@@ -47,7 +47,7 @@ struct Layout {
 int blocks_of(const pdbm_params &p)
 {
     const int64_t cellb = ((int64_t)p.nr * p.ntheta + BLOCK - 1) / BLOCK;
-    const int rows = rows_per_wave(p.nr, p.ntheta);
+    const int rows = rows_per_wave(p.nr, p.ntheta, p.precision == PDBM_FP32);
     const int64_t waves = (int64_t)((p.nr + rows - 1) / rows) * ((p.ntheta + STRIP - 1) / STRIP);
     const int64_t stepb = (waves + BLOCK / 64 - 1) / (BLOCK / 64);
     return (int)(cellb > stepb ? cellb : stepb);
@@ -63,10 +63,11 @@ Layout layout_of(const pdbm_params &p)
     L.f = align256((size_t)NQ * cells_p * L.esz);
     L.lam = align256(cells_p * sizeof(double));
     L.cs = align256((size_t)p.ntheta * sizeof(double2));
+    L.desc = align256(sizeof(SolveDesc));
     L.partials = align256((size_t)L.nblocks * 5 * sizeof(double));
     L.counter = 256;
     L.hist = align256((size_t)(HIST_CAP + 1) * sizeof(pdbm_diag));
-    L.total = 2 * L.f + 2 * L.lam + L.cs + L.partials + L.counter + L.hist;
+    L.total = 2 * L.f + 2 * L.lam + L.cs + L.desc + L.partials + L.counter + L.hist;
     return L;
 }
 
@@ -74,20 +75,23 @@ bool is_fin(double x) { return std::isfinite(x); }
 
 }  // namespace
 
-// Rows per wavefront: enough wavefronts to fill the chip about twice over at
-// two per SIMD, but at least 2 rows so the two bounding rows stay a minor
-// share of the loads.  PDBM_ROWS_PER_WAVE overrides it (tuning).
-int pdbm::rows_per_wave(int nr, int nt)
+// Rows per wavefront: just enough wavefronts for one resident wave of the
+// whole grid (256 CUs x 4 SIMDs x the step kernel's occupancy: 1 wavefront
+// per SIMD in float64, 2 in float32), so that every wavefront marches the
+// longest possible column and none waits for a second round.
+// PDBM_ROWS_PER_WAVE overrides it (tuning).
+int pdbm::rows_per_wave(int nr, int nt, bool fp32)
 {
     static const int env = [] {
         const char *e = std::getenv("PDBM_ROWS_PER_WAVE");
         return e ? std::atoi(e) : 0;
     }();
     if (env > 0) return env;
+    const int64_t slots = 256 * 4 * (fp32 ? 2 : 1);
     const int64_t strips = (nt + STRIP - 1) / STRIP;
-    int64_t rows = (int64_t)nr * strips / 4096;
+    int64_t rows = ((int64_t)nr * strips + slots - 1) / slots;
     if (rows < 2) rows = 2;
-    if (rows > 64) rows = 64;
+    while (strips * ((nr + rows - 1) / rows) > slots) ++rows;
     return (int)rows;
 }
 
@@ -139,6 +143,11 @@ int pdbm_validate(const pdbm_params *p, const pdbm_ic *ic, double *cfl)
     if (p->nr < 1 || p->ntheta < 1) return fail(PDBM_EINVAL, "nr and ntheta must be >= 1");
     if ((int64_t)p->nr * p->ntheta > MAX_CELLS) return fail(PDBM_EINVAL, "grid larger than 2^24 cells");
     if (p->sector < 1 || p->sector > 8) return fail(PDBM_EINVAL, "sector must be in 1..8");
+    {
+        const size_t esz = p->precision == PDBM_FP32 ? 4 : 8;
+        if ((size_t)NQ * p->nr * pitch_of(p->ntheta) * esz >= ((size_t)1 << 32))
+            return fail(PDBM_EINVAL, "f array of one solve must stay below 4 GiB");
+    }
     if (p->precision != PDBM_FP64 && p->precision != PDBM_FP32) return fail(PDBM_EINVAL, "unknown precision");
     if (p->m < 0 || p->n < 0 || p->m > 64 || p->n > 64) return fail(PDBM_EINVAL, "m, n must be in 0..64");
     if (p->diag_every < 0) return fail(PDBM_EINVAL, "diag_every must be >= 0");
@@ -219,6 +228,7 @@ struct pdbm_solver {
     void *f[2] = {nullptr, nullptr};
     double *lam[2] = {nullptr, nullptr};
     double2 *cs = nullptr;
+    SolveDesc *ddesc = nullptr;  // device copy read by the step kernel
     double *partials = nullptr;
     unsigned *counter = nullptr;
     pdbm_diag *hist = nullptr;  // [HIST_CAP] ring + 1 slot for pdbm_moments
@@ -243,7 +253,7 @@ struct pdbm_solver {
         d.n = p.n;
         d.disc = p.r_min == 0.0;
         d.reacts = (p.w1 > 0.0 || p.w2 > 0.0) ? 1 : 0;
-        d.rows = rows_per_wave(p.nr, p.ntheta);
+        d.rows = rows_per_wave(p.nr, p.ntheta, p.precision == PDBM_FP32);
         d.plane = (int64_t)p.nr * L.pitch;
         d.dr = (p.r_max - p.r_min) / p.nr;
         d.dth = p.sector * M_PI / 4.0 / p.ntheta;
@@ -326,6 +336,8 @@ int pdbm_create(const pdbm_params *p, const pdbm_ic *ic, void *workspace, size_t
     q += s->L.lam;
     s->cs = (double2 *)q;
     q += s->L.cs;
+    s->ddesc = (SolveDesc *)q;
+    q += s->L.desc;
     s->partials = (double *)q;
     q += s->L.partials;
     s->counter = (unsigned *)q;
@@ -348,6 +360,8 @@ int pdbm_create(const pdbm_params *p, const pdbm_ic *ic, void *workspace, size_t
     }
     hipError_t e = hipMemcpyAsync(s->cs, cs.data(), cs.size() * sizeof(double2), hipMemcpyHostToDevice, s->st);
     if (e == hipSuccess) e = hipMemcpyAsync(s->counter, &zero, sizeof zero, hipMemcpyHostToDevice, s->st);
+    const SolveDesc hd = s->desc(0);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->ddesc, &hd, sizeof hd, hipMemcpyHostToDevice, s->st);
     if (e == hipSuccess) {
         // the initial state goes to buffer 0: a desc reading 1 writes 0
         e = launch_init_ic(s->desc(1), s->fp32, *ic, s->st);
@@ -391,7 +405,7 @@ int pdbm_step(pdbm_solver *s, int64_t nsteps)
     for (int64_t i = 0; i < nsteps; ++i) {
         const bool rec = s->p.diag_every > 0 && s->step % s->p.diag_every == 0;
         pdbm_diag *slot = s->hist + (s->nrec % HIST_CAP);
-        HIPCHK(launch_step(s->desc(s->cur), s->fp32, s->diag(slot, rec), s->st));
+        HIPCHK(launch_step(s->desc(s->cur), s->ddesc, s->fp32, s->diag(slot, rec), s->st));
         s->cur ^= 1;
         s->step++;
         if (rec) s->nrec++;

@@ -35,6 +35,14 @@ struct SolveDesc {
     double A[16];  // F_k(T) = sum_n A[(k-1)*4+n-1] T^n
 };
 
+// The two f and lambda buffers of one step (they swap every step).
+struct StepBufs {
+    const void *f_in;
+    void *f_out;
+    const double *lam_in;
+    double *lam_out;
+};
+
 // Drift-report reduction state of one solve.
 struct DiagCtl {
     double *partials;    // [nblocks][5]
@@ -47,13 +55,15 @@ struct DiagCtl {
 
 // Kernel launchers (pdbm_kernels.hip).  All enqueue on `st` and return the
 // hipError_t of the launch.
-hipError_t launch_step(const SolveDesc &d, bool fp32, const DiagCtl &dc, hipStream_t st);
+// The step kernel reads the solve's description from device memory
+// (dev_desc, a copy of d); d's buffer pointers give this step's buffers.
+hipError_t launch_step(const SolveDesc &d, const SolveDesc *dev_desc, bool fp32, const DiagCtl &dc, hipStream_t st);
 hipError_t launch_init_ic(const SolveDesc &d, bool fp32, const pdbm_ic &ic, hipStream_t st);
 hipError_t launch_init_fields(const SolveDesc &d, bool fp32, const double *fields, hipStream_t st);
 hipError_t launch_moments(const SolveDesc &d, bool fp32, double *out, const DiagCtl &dc, hipStream_t st);
 int cell_blocks(const SolveDesc &d);
 int step_blocks(const SolveDesc &d);
 // Rows per wavefront of the step kernel for an nr x nt grid.
-int rows_per_wave(int nr, int nt);
+int rows_per_wave(int nr, int nt, bool fp32);
 
 }  // namespace pdbm

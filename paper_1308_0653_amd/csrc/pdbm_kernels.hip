@@ -210,7 +210,8 @@ __device__ __forceinline__ void diag_cell(double v[5], double rho, double ux, do
 // ------------------------------------------------------------------ step --
 // Cross-lane moves within a wavefront (DPP wave shifts): the value held by
 // lane-1 (from_left) and by lane+1 (from_right).  Lanes 0 / 63 receive 0; they
-// are halo lanes whose results are never stored.
+// are halo lanes whose results are never stored.  Call these only where every
+// lane of the wavefront is active (never inside a divergent branch).
 __device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
 __device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
 __device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
@@ -224,61 +225,127 @@ __device__ __forceinline__ double from_right(double v)
     return __hiloint2double(dpp_shl1(__double2hiint(v)), dpp_shl1(__double2loint(v)));
 }
 
+// The step kernel reads the solve description through the constant address
+// space: it is never written while a step runs, so the loads are scalar.  The
+// kernel parameter stays a plain pointer (host and device must see the same
+// kernel signature) and is cast inside device code.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) SolveDesc *DescPtr;
+#else
+typedef const SolveDesc *DescPtr;
+#endif
+
+// Raw buffer access to the f and lambda arrays: the lane's column offset is a
+// loop-invariant VGPR, the row and velocity-plane offsets a scalar register
+// (arrays stay below 4 GiB, which create() checks).
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)0xFFFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ void bload(float &v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    v = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ __forceinline__ void bload(double &v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    const i32x2 t = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    v = __hiloint2double(t.y, t.x);
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, vo, so, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    i32x2 t;
+    t.x = __double2loint(v);
+    t.y = __double2hiint(v);
+    __builtin_amdgcn_raw_buffer_store_b64(t, r, vo, so, 0);
+}
+// Keeps a scalar offset opaque to the optimiser, so that the 33 plane offsets
+// are re-derived by one scalar add each instead of being hoisted out of the
+// row loop (where they would not fit in scalar registers).
+__device__ __forceinline__ uint32_t opaque(uint32_t x)
+{
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
 // A wavefront owns a strip of STRIP consecutive theta columns plus one halo
-// column on each side (lanes 0 and 63), and marches outward over a block of
-// rows.  Rows i and i+1 of f are held in registers and row i-1 in a
-// lane-private LDS slot: the radial neighbours come from there, the azimuthal
-// ones from the adjacent lanes, so every f value is read from memory once per
-// step (plus the halo columns and the two rows bounding the block).  Row i+1
-// is requested before row i is computed, which keeps one row of loads in
-// flight per wavefront.
+// column on each side (lanes 0 and 63), and marches outward (or inward) over
+// a block of rows.  The row being computed and the next two in marching order
+// are held in registers, the row behind in a lane-private LDS slot: radial
+// neighbours come from there, azimuthal ones from the adjacent lanes, so each
+// f value is read from memory once per step (plus the halo columns and the
+// two rows bounding the block).  The second row ahead is requested a whole
+// row of compute before it is first needed.
 template <typename real, bool ROT>
 struct Strip {
-    const SolveDesc &d;
-    const real *__restrict__ fin;
-    real *__restrict__ fout;
-    int lane, col, pc, rot;  // column, physical column, direction shift of this lane's data
+    DescPtr dp;
+    __amdgpu_buffer_rsrc_t fin, fout, lin, lout;
+    uint32_t vo, vol;     // byte offsets of this lane's column in f and lambda rows
+    uint32_t row_bytes, lrow_bytes, plane_bytes;
+    int lane, pc, rot;    // physical column, direction shift of this lane's data
     bool useful;
 
-    __device__ __forceinline__ Strip(const SolveDesc &d_, int strip) : d(d_)
+    __device__ __forceinline__ Strip(DescPtr dp_, const StepBufs &b, int strip) : dp(dp_)
     {
-        fin = (const real *)d.f_in;
-        fout = (real *)d.f_out;
+        fin = rsrc_of(b.f_in);
+        fout = rsrc_of(b.f_out);
+        lin = rsrc_of(b.lam_in);
+        lout = rsrc_of(b.lam_out);
+        const int nt = dp->nt;
         lane = threadIdx.x & 63;
-        col = strip * STRIP - 1 + lane;
-        const int wraps = col < 0 ? -1 : col / d.nt;  // periodic images of the sector
-        pc = col - wraps * d.nt;
-        rot = ROT ? ((-wraps * d.sector) & 7) : 0;
-        useful = lane >= 1 && lane <= STRIP && col < d.nt;
+        const int col = strip * STRIP - 1 + lane;
+        const int wraps = col < 0 ? -1 : col / nt;  // periodic images of the sector
+        pc = col - wraps * nt;
+        rot = ROT ? ((-wraps * dp->sector) & 7) : 0;
+        useful = lane >= 1 && lane <= STRIP && col < nt;
+        vo = (uint32_t)pc * (uint32_t)sizeof(real);
+        vol = (uint32_t)pc * 8u;
+        row_bytes = (uint32_t)dp->pitch * (uint32_t)sizeof(real);
+        lrow_bytes = (uint32_t)dp->pitch * 8u;
+        plane_bytes = (uint32_t)dp->plane * (uint32_t)sizeof(real);
     }
-
-    // plane of direction `dir` of speed ring `base` as seen by this lane
-    __device__ __forceinline__ int plane(int base, int dir) const { return ROT ? base + ((dir + rot) & 7) : base + dir; }
 
     __device__ __forceinline__ void load_row(int row, real f[NQ], double &lam) const
     {
-        const int64_t off = (int64_t)row * d.pitch + pc;
-        f[0] = fin[off];
+        uint32_t so = (uint32_t)row * row_bytes;
+        if (ROT) {
+            // this lane's data of direction dir lives in plane (dir + rot) % 8
+            bload(f[0], fin, vo, so);
 #pragma unroll
-        for (int k = 1; k <= 4; ++k)
-#pragma unroll
-            for (int dir = 0; dir < 8; ++dir) {
-                const int base = 1 + 8 * (k - 1);
-                f[base + dir] = fin[(int64_t)plane(base, dir) * d.plane + off];
+            for (int q = 1; q < NQ; ++q) {
+                const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8;
+                bload(f[q], fin, vo + (uint32_t)(base + ((dir + rot) & 7)) * plane_bytes, so);
             }
-        lam = d.lam_in[off];
+        } else {
+            bload(f[0], fin, vo, so);
+#pragma unroll
+            for (int q = 1; q < NQ; ++q) {
+                so = opaque(so + plane_bytes);
+                bload(f[q], fin, vo, so);
+            }
+        }
+        bload(lam, lin, vol, (uint32_t)row * lrow_bytes);
     }
 };
 
 // One row of one strip: moments, F_k(T), f^eq, BGK + chemical term, Cochran
-// lambda, donor-cell fluxes of f and lambda.  prev (LDS, this lane's column):
-// row i-1, replaced by row i as it is consumed; fc, fn: rows i, i+1.
+// lambda, donor-cell fluxes of f and lambda.  fc: row i.  Marching outward
+// (down = false): prev (LDS, this lane's column) holds row i-1 and fn row
+// i+1; marching inward the roles swap.  prev is replaced by row i as it is
+// consumed.  mr[dd] / mt[dd]: which side is upwind for direction dd (its
+// opposite dd+4 takes the other side).
 template <typename real, bool ROT>
-__device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, volatile real (*prev)[64], const real fc[NQ],
-                                           const real fn[NQ], double lp, double lc, double ln, real cth, real sth,
-                                           double csx, double csy, double red[5], bool diag)
+__device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, real (*prev)[64], const real fc[NQ],
+                                           const real fn[NQ], double lbehind, double lc, double lahead,
+                                           const bool mr[4], const bool mt[4], const real acr[4], const real ctv[4],
+                                           bool lr_behind, double csx, double csy, double red[5], bool diag)
 {
-    const SolveDesc &d = S.d;
+    const DescPtr dp = S.dp;
     // (1) moments
     real rho, jx, jy, e;
     raw_moments(fc, rho, jx, jy, e);
@@ -290,39 +357,41 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, vo
 
     // (2) weights and f^eq polynomial
     real F[5];
-    weights(d.A, Td, F);
+    weights(dp->A, Td, F);
     const EqPoly<real> EP(ux, uy, u2, T);
 
     // (3) Cochran rate, gated by the ignition temperature (float64)
     double a = 0.0, b = 0.0, R = 0.0;
-    const bool on = d.reacts && Td > d.T_th;
+    const bool on = dp->reacts && Td > dp->T_th;
     if (on) {
         const double p = (double)rho * Td;
-        a = d.w1 * ipow(p, d.m);
-        b = d.w2 * ipow(p, d.n);
+        a = dp->w1 * ipow(p, dp->m);
+        b = dp->w2 * ipow(p, dp->n);
         R = (1.0 - lc) * (a + b * lc);
     }
     // M dt = f^eq * beta * (|v-u|^2 - 2T), beta = Q R dt / (2 T^2) (D = 2)
-    const real beta = (real)(d.Q * R * d.dt / (2.0 * Td * Td));
-    const real omega = (real)d.omega;
+    const real beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
+    const real omega = (real)dp->omega;
     const real keep = (real)1 - omega;
     const real Bz = (real)-2 * beta * T;
 
-    // Courant numbers: polar components of directions dd = 0..3 at theta_j,
-    // v_r = v (cos(dd pi/4) cos th + sin(dd pi/4) sin th),
-    // v_theta = v (sin(dd pi/4) cos th - cos(dd pi/4) sin th); dd+4 is the negative
-    const double ri = d.r_min + ((double)ir + 0.5) * d.dr;
-    const real kr = (real)d.dt_dr, kt = (real)(d.dt_dth / ri);
-    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
-    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    // azimuthal Courant magnitudes of this row (the geometric 1/r term)
+    const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
+    const real kt = (real)(dp->dt_dth / ri);
+    real act[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) act[dd] = fabs(ctv[dd]) * kt;
 
     const bool store = S.useful;
-    const int64_t off = (int64_t)ir * d.pitch + S.pc;
-    real *__restrict__ fout = S.fout;
+    const int lane = S.lane;
+    // output plane q of this row sits at rowoff + q * pb (pb re-derived per
+    // row so the 33 products stay scalar arithmetic inside the loop)
+    const uint32_t rowoff = (uint32_t)ir * S.row_bytes;
+    const uint32_t pb = opaque(S.plane_bytes);
 
     // rest particle: no streaming
-    if (store) fout[off] = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * fc[0];
-    const int lane = S.lane;
+    const real rest = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * fc[0];
+    if (store) bstore(rest, S.fout, S.vo, rowoff);
 
 #pragma unroll
     for (int k = 1; k <= 4; ++k) {
@@ -339,22 +408,23 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, vo
 #pragma unroll
             for (int sgn = 0; sgn < 2; ++sgn) {
                 const int q = base + dd + 4 * sgn;
-                const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * fc[q] : rF * pm * (Ak - bz) + omega * fc[q];
-                // upwind neighbour: C >= 0 takes the lower one (Sec. II.C)
-                const real cr = sgn == 0 ? crv[dd] : -crv[dd];
-                const real ct = sgn == 0 ? ctv[dd] : -ctv[dd];
-                const real below = prev[q][lane];
-                prev[q][lane] = fc[q];
-                const real nbr = cr >= (real)0 ? below : fn[q];
-                const real left = from_left(fc[q]), right = from_right(fc[q]);
-                const real nbt = ct >= (real)0 ? left : right;
                 const real x = fc[q];
-                const real out = coll - v * (fabs(cr) * kr * (x - nbr) + fabs(ct) * kt * (x - nbt));
-                if (store) fout[(int64_t)q * d.plane + off] = out;
+                const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * x : rF * pm * (Ak - bz) + omega * x;
+                // upwind neighbours: C >= 0 takes the lower one (Sec. II.C)
+                const real behind = prev[q][lane];
+                prev[q][lane] = x;
+                const bool rb = sgn == 0 ? mr[dd] : !mr[dd];
+                const real nbr = rb ? behind : fn[q];
+                // both shifts are taken by every lane (a DPP read of a lane
+                // switched off by a branch would return 0), then selected
+                const real left = from_left(x), right = from_right(x);
+                const bool tl = sgn == 0 ? mt[dd] : !mt[dd];
+                const real nbt = tl ? left : right;
+                const real out = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+                // stored lanes are never rotated sector images
+                if (store) bstore(out, S.fout, S.vo, rowoff + (uint32_t)q * pb);
             }
         }
-        // keep the scheduler from interleaving the rings (register pressure)
-        __builtin_amdgcn_sched_barrier(0);
     }
 
     // (4) lambda: closed-form Cochran step, then upwind by own-cell u
@@ -363,63 +433,92 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, vo
     const double utp = -uxd * csy + uyd * csx;
     double lreac = lc;
     if (on && a + b > 0.0) {
-        const double q1 = (1.0 - lc) * exp(-(a + b) * d.dt);
+        const double q1 = (1.0 - lc) * exp(-(a + b) * dp->dt);
         lreac = 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
     }
     const double lleft = from_left(lc), lright = from_right(lc);
-    const double lr = urp >= 0.0 ? lp : ln;
+    const double lr = (urp >= 0.0) == lr_behind ? lbehind : lahead;
     const double lt = utp >= 0.0 ? lleft : lright;
-    if (store) d.lam_out[off] = lreac - fabs(urp) * d.dt_dr * (lc - lr) - fabs(utp) * (d.dt_dth / ri) * (lc - lt);
+    const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
+    if (store) bstore(lnew, S.lout, S.vol, (uint32_t)ir * S.lrow_bytes);
 
-    if (diag && store) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lc, ri * d.dr * d.dth, d.Q);
+    if (diag && store) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lc, ri * dp->dr * dp->dth, dp->Q);
 }
 
-// Work of one wavefront: strip `strip`, rows [i0, i1).  prev: this
-// wavefront's [NQ][64] LDS slots.
+// Row `row` of the strip into f, or a ghost row outside [0, nr): below r_min
+// the zero-gradient copy of row 0 or the disc-centre rule f(-1, j, k, i) =
+// f(0, j, k, (i+4)%8) (Sec. II.D); above r_max the zero-gradient copy of row
+// nr-1.  `edge` holds the boundary row the ghost copies.
 template <typename real, bool ROT>
-__device__ __forceinline__ void march(const SolveDesc &d, int strip, int i0, int i1, volatile real (*prev)[64], double red[5],
-                                      bool diag)
+__device__ __forceinline__ void row_or_ghost(const Strip<real, ROT> &S, int row, real f[NQ], double &lam,
+                                             const real edge[NQ], double ledge)
 {
-    const Strip<real, ROT> S(d, strip);
-    const int lane = S.lane;
-    const double2 cs = d.cs[S.pc];
-    const real cth = (real)cs.x, sth = (real)cs.y;
-    real fc[NQ], fn[NQ];
-    double lp, lc, ln;
-    S.load_row(i0, fc, lc);
-    if (i0 > 0) {
-        S.load_row(i0 - 1, fn, lp);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) prev[q][lane] = fn[q];
-    } else {
-        // ghost row below r_min: zero gradient, or the disc-centre rule
-        // f(-1, j, k, i) = f(0, j, k, (i+4)%8) (Sec. II.D)
-        prev[0][lane] = fc[0];
-#pragma unroll
-        for (int q = 1; q < NQ; ++q) {
-            const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8;
-            prev[q][lane] = d.disc ? fc[base + ((dir + 4) & 7)] : fc[q];
-        }
-        lp = lc;
+    if (row >= 0 && row < S.dp->nr) {
+        S.load_row(row, f, lam);
+        return;
     }
-    for (int ir = i0; ir < i1; ++ir) {
-        if (ir + 1 < d.nr) {
-            S.load_row(ir + 1, fn, ln);
-        } else {  // zero-gradient ghost row above r_max
+    const bool disc = row < 0 && S.dp->disc;
+    f[0] = edge[0];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) fn[q] = fc[q];
-            ln = lc;
+    for (int q = 1; q < NQ; ++q) {
+        const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8;
+        f[q] = disc ? edge[base + ((dir + 4) & 7)] : edge[q];
+    }
+    lam = ledge;
+}
+
+// Work of one wavefront: strip `strip`, rows [i0, i1), marched outward or,
+// with `down`, inward.  prev: this wavefront's [NQ][64] LDS slots.
+template <typename real, bool ROT>
+__device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
+                                      real (*prev)[64], double red[5], bool diag)
+{
+    const Strip<real, ROT> S(dp, bufs, strip);
+    const int lane = S.lane;
+    const double2 cs = dp->cs[S.pc];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    // polar components of directions dd = 0..3 at theta_j (dd+4 is the negative):
+    // v_r = v (cos(dd pi/4) cos th + sin(dd pi/4) sin th),
+    // v_theta = v (sin(dd pi/4) cos th - cos(dd pi/4) sin th)
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    const real kr = (real)dp->dt_dr;
+    real acr[4];
+    bool mr[4], mt[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        acr[dd] = fabs(crv[dd]) * kr;
+        mr[dd] = (crv[dd] >= (real)0) != down;  // true: the upwind radial neighbour is the row behind
+        mt[dd] = ctv[dd] >= (real)0;            // true: the upwind azimuthal neighbour is lane-1
+    }
+    const int step = down ? -1 : 1;
+    const int first = down ? i1 - 1 : i0;
+    const int count = i1 - i0;
+    real fc[NQ], fn[NQ], fnn[NQ];
+    double lp, lc, ln, lnn;
+    S.load_row(first, fc, lc);
+    row_or_ghost(S, first + step, fn, ln, fc, lc);
+    row_or_ghost(S, first - step, fnn, lp, fc, lc);  // the row behind the first
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) prev[q][lane] = fnn[q];
+    int ir = first;
+    for (int n = 0; n < count; ++n, ir += step) {
+        row_or_ghost(S, ir + 2 * step, fnn, lnn, fn, ln);
+        update_row<real, ROT>(S, ir, prev, fc, fn, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, red, diag);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            fc[q] = fn[q];
+            fn[q] = fnn[q];
         }
-        update_row<real, ROT>(S, ir, prev, fc, fn, lp, lc, ln, cth, sth, cs.x, cs.y, red, diag);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) fc[q] = fn[q];
         lp = lc;
         lc = ln;
+        ln = lnn;
+        // Compiler-only barrier: the LDS slots must not be promoted to
+        // registers across iterations (they exist to free those registers).
+        asm volatile("" ::: "memory");
     }
 }
 
-// One time step of a whole solve.  Wave w of the grid takes tile t = (its
-// block's XCD-ordered index) * 4 + w: strip t / nrb, row block t % nrb.
 // Occupancy: float32 rows fit two wavefronts per SIMD; float64 rows take
 // the whole register file of one (the next row in flight is 66 VGPRs).
 template <typename real>
@@ -427,22 +526,32 @@ struct StepOcc {
     static constexpr int waves = sizeof(real) == 4 ? 2 : 1;
 };
 
+// One time step of a whole solve.  Wave w of the grid takes tile t = (its
+// block's XCD-ordered index) * 4 + w: row block t / nstrip, strip t % nstrip.
 template <typename real, bool ROT>
-__global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(SolveDesc d, DiagCtl dc)
+__global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const SolveDesc *desc, StepBufs bufs, DiagCtl dc)
 {
+    const DescPtr dp = (DescPtr)desc;
     const int nb = gridDim.x;
     const int blk = xcd_tile(blockIdx.x, nb);
-    const int t = blk * (BLOCK / 64) + (threadIdx.x >> 6);
-    const int nrb = (d.nr + d.rows - 1) / d.rows;
-    const int nstrip = (d.nt + STRIP - 1) / STRIP;
+    // wave-uniform by construction; tell the compiler so that the row loop
+    // and the offsets derived from it live in scalar registers
+    const int t = __builtin_amdgcn_readfirstlane(blk * (BLOCK / 64) + (threadIdx.x >> 6));
+    const int rows = dp->rows, nr = dp->nr;
+    const int nrb = (nr + rows - 1) / rows;
+    const int nstrip = (dp->nt + STRIP - 1) / STRIP;
     __shared__ real prev[BLOCK / 64][NQ][64];
     double red[5] = {0, 0, 0, 0, 0};
     const bool diag = dc.enabled != 0;
     if (t < nrb * nstrip) {
-        const int strip = t / nrb, rb = t - strip * nrb;
-        const int i0 = rb * d.rows;
-        const int i1 = min(i0 + d.rows, d.nr);
-        march<real, ROT>(d, strip, i0, i1, prev[threadIdx.x >> 6], red, diag);
+        // row-block major: the strips of one row block sit side by side in
+        // the same XCD and share their halo columns in its L2; odd row blocks
+        // march inward so that the rows bounding two blocks are read by both
+        // at the same time.
+        const int rb = t / nstrip, strip = t - rb * nstrip;
+        const int i0 = rb * rows;
+        const int i1 = min(i0 + rows, nr);
+        march<real, ROT>(dp, bufs, strip, i0, i1, (rb & 1) != 0, prev[threadIdx.x >> 6], red, diag);
     }
     if (diag) diag_reduce(dc, red, blk, nb);
 }
@@ -558,20 +667,21 @@ int step_blocks(const SolveDesc &d)
     return (int)((nrb * nstrip + BLOCK / 64 - 1) / (BLOCK / 64));
 }
 
-hipError_t launch_step(const SolveDesc &d, bool fp32, const DiagCtl &dc, hipStream_t st)
+hipError_t launch_step(const SolveDesc &d, const SolveDesc *dev_desc, bool fp32, const DiagCtl &dc, hipStream_t st)
 {
     const int nb = step_blocks(d);
     const bool rot = d.sector != 8;
+    const StepBufs b{d.f_in, d.f_out, d.lam_in, d.lam_out};
     if (fp32) {
         if (rot)
-            hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, d, dc);
+            hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, dev_desc, b, dc);
         else
-            hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, d, dc);
+            hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, dev_desc, b, dc);
     } else {
         if (rot)
-            hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, d, dc);
+            hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, dev_desc, b, dc);
         else
-            hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, d, dc);
+            hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, dev_desc, b, dc);
     }
     return hipGetLastError();
 }
