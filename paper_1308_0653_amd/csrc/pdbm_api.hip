@@ -254,7 +254,8 @@ struct pdbm_solver {
         d.disc = p.r_min == 0.0;
         d.reacts = (p.w1 > 0.0 || p.w2 > 0.0) ? 1 : 0;
         d.rows = rows_per_wave(p.nr, p.ntheta, p.precision == PDBM_FP32);
-        d.plane = (int64_t)p.nr * L.pitch;
+        d.plane = L.pitch;
+        d.rstride = (int64_t)NQ * L.pitch;
         d.dr = (p.r_max - p.r_min) / p.nr;
         d.dth = p.sector * M_PI / 4.0 / p.ntheta;
         d.r_min = p.r_min;
@@ -463,6 +464,33 @@ int pdbm_diag_history(pdbm_solver *s, pdbm_diag *out, int32_t cap, int32_t *n)
     return PDBM_OK;
 }
 
+// f on the device is [nr][NQ][pitch]; host arrays are [NQ][nr][ntheta].
+static hipError_t f_to_host(pdbm_solver *s, void *host)
+{
+    const int nr = s->p.nr, nt = s->p.ntheta;
+    const size_t esz = s->L.esz, pitch = s->L.pitch;
+    for (int q = 0; q < NQ; ++q) {
+        hipError_t e = hipMemcpy2D((char *)host + (size_t)q * nr * nt * esz, nt * esz,
+                                   (const char *)s->f[s->cur] + q * pitch * esz, NQ * pitch * esz, nt * esz, nr,
+                                   hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static hipError_t f_to_device(pdbm_solver *s, const void *host)
+{
+    const int nr = s->p.nr, nt = s->p.ntheta;
+    const size_t esz = s->L.esz, pitch = s->L.pitch;
+    for (int q = 0; q < NQ; ++q) {
+        hipError_t e = hipMemcpy2D((char *)s->f[s->cur] + q * pitch * esz, NQ * pitch * esz,
+                                   (const char *)host + (size_t)q * nr * nt * esz, nt * esz, nt * esz, nr,
+                                   hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 int pdbm_read_f(pdbm_solver *s, double *f, double *lam)
 {
     if (!s) return fail(PDBM_EINVAL, "NULL solver");
@@ -472,12 +500,10 @@ int pdbm_read_f(pdbm_solver *s, double *f, double *lam)
     if (f) {
         if (s->fp32) {
             std::vector<float> tmp((size_t)NQ * ncell);
-            HIPCHK(hipMemcpy2D(tmp.data(), nt * sizeof(float), s->f[s->cur], pitch * sizeof(float), nt * sizeof(float),
-                               (size_t)NQ * nr, hipMemcpyDeviceToHost));
+            HIPCHK(f_to_host(s, tmp.data()));
             for (size_t i = 0; i < tmp.size(); ++i) f[i] = tmp[i];
         } else {
-            HIPCHK(hipMemcpy2D(f, nt * sizeof(double), s->f[s->cur], pitch * sizeof(double), nt * sizeof(double),
-                               (size_t)NQ * nr, hipMemcpyDeviceToHost));
+            HIPCHK(f_to_host(s, f));
         }
     }
     if (lam)
@@ -496,11 +522,9 @@ int pdbm_write_f(pdbm_solver *s, const double *f, const double *lam, int64_t ste
         if (s->fp32) {
             std::vector<float> tmp((size_t)NQ * ncell);
             for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)f[i];
-            HIPCHK(hipMemcpy2D(s->f[s->cur], pitch * sizeof(float), tmp.data(), nt * sizeof(float), nt * sizeof(float),
-                               (size_t)NQ * nr, hipMemcpyHostToDevice));
+            HIPCHK(f_to_device(s, tmp.data()));
         } else {
-            HIPCHK(hipMemcpy2D(s->f[s->cur], pitch * sizeof(double), f, nt * sizeof(double), nt * sizeof(double),
-                               (size_t)NQ * nr, hipMemcpyHostToDevice));
+            HIPCHK(f_to_device(s, f));
         }
     }
     if (lam)
@@ -535,8 +559,7 @@ int pdbm_get_state(pdbm_solver *s, void *buf, size_t *bytes)
     std::memcpy(buf, &h, sizeof h);
     char *fdst = (char *)buf + sizeof h;
     HIPCHK(hipStreamSynchronize(s->st));
-    HIPCHK(hipMemcpy2D(fdst, nt * s->L.esz, s->f[s->cur], pitch * s->L.esz, nt * s->L.esz, (size_t)NQ * nr,
-                       hipMemcpyDeviceToHost));
+    HIPCHK(f_to_host(s, fdst));
     HIPCHK(hipMemcpy2D(fdst + fb, nt * sizeof(double), s->lam[s->cur], pitch * sizeof(double), nt * sizeof(double),
                        nr, hipMemcpyDeviceToHost));
     *bytes = need;
@@ -555,8 +578,7 @@ int pdbm_set_state(pdbm_solver *s, const void *buf, size_t bytes)
         return fail(PDBM_EINVAL, "checkpoint does not match this solve");
     const char *src = (const char *)buf + sizeof h;
     HIPCHK(hipStreamSynchronize(s->st));
-    HIPCHK(hipMemcpy2D(s->f[s->cur], pitch * s->L.esz, src, nt * s->L.esz, nt * s->L.esz, (size_t)NQ * nr,
-                       hipMemcpyHostToDevice));
+    HIPCHK(f_to_device(s, src));
     HIPCHK(hipMemcpy2D(s->lam[s->cur], pitch * sizeof(double), src + fb, nt * sizeof(double), nt * sizeof(double),
                        nr, hipMemcpyHostToDevice));
     s->step = h.step;

@@ -19,7 +19,7 @@ constexpr int STRIP = 62;       // theta columns stored per wavefront (64 lanes 
 // kernel argument (one solve per launch) or read from a device table (packed
 // launches over many solves).
 struct SolveDesc {
-    const void *f_in;  // [NQ][nr][pitch] of float or double
+    const void *f_in;  // [nr][NQ][pitch] of float or double: the 33 velocity rows of one r row are adjacent
     void *f_out;
     const double *lam_in;  // [nr][pitch]
     double *lam_out;
@@ -27,7 +27,8 @@ struct SolveDesc {
     int32_t nr, nt, pitch, sector;
     int32_t m, n, disc, reacts;  // disc: r_min == 0; reacts: w1+w2 > 0
     int32_t rows, pad_;          // rows marched by one wavefront per step
-    int64_t plane;               // nr * pitch, elements per velocity plane
+    int64_t plane;               // elements between the rows of consecutive velocities (= pitch)
+    int64_t rstride;             // elements between consecutive r rows of f (= NQ * pitch)
     double r_min, dr, dth;
     double dt_dr, dt_dth;  // dt/dr, dt/dtheta
     double omega;          // exp(-dt/tau)

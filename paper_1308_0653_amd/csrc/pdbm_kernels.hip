@@ -305,7 +305,7 @@ struct Strip {
         useful = lane >= 1 && lane <= STRIP && col < nt;
         vo = (uint32_t)pc * (uint32_t)sizeof(real);
         vol = (uint32_t)pc * 8u;
-        row_bytes = (uint32_t)dp->pitch * (uint32_t)sizeof(real);
+        row_bytes = (uint32_t)dp->rstride * (uint32_t)sizeof(real);
         lrow_bytes = (uint32_t)dp->pitch * 8u;
         plane_bytes = (uint32_t)dp->plane * (uint32_t)sizeof(real);
     }
@@ -569,9 +569,10 @@ __global__ __launch_bounds__(BLOCK) void k_moments(SolveDesc d, double *out, Dia
         const int jt = c - ir * d.nt;
         const real *fin = (const real *)d.f_in;
         const int64_t idx = (int64_t)ir * d.pitch + jt;
+        const int64_t fidx = (int64_t)ir * d.rstride + jt;
         real f[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) f[q] = fin[q * d.plane + idx];
+        for (int q = 0; q < NQ; ++q) f[q] = fin[q * d.plane + fidx];
         real rho, jx, jy, e;
         raw_moments(f, rho, jx, jy, e);
         const double rd = (double)rho;
@@ -620,9 +621,9 @@ __device__ __forceinline__ void store_eq(const SolveDesc &d, int64_t idx, int jt
     const double ux = ur * cs.x - ut * cs.y, uy = ur * cs.y + ut * cs.x;
     real f[NQ];
     equilibrium<real>(d.A, (real)rho, (real)ux, (real)uy, (real)T, f);
-    real *fo = (real *)d.f_out;
+    real *fo = (real *)d.f_out + (idx / d.pitch) * d.rstride + jt;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) fo[q * d.plane + idx] = f[q];
+    for (int q = 0; q < NQ; ++q) fo[q * d.plane] = f[q];
 }
 
 template <typename real>
