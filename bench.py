@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+PROFILE = os.path.join(ROOT, "profiles", "k_step_outward1024.md")
+KERNEL_SOURCES = ("paper_1308_0653_amd/csrc/pdbm_kernels.hip", "paper_1308_0653_amd/csrc/pdbm_internal.h")
 # Algorithmic bytes per cell-update: read and write all 33 f values and lambda.
 BYTES_PER_CELL = {"f64": 33 * 8 * 2 + 8 * 2, "f32": 33 * 4 * 2 + 8 * 2}
 
@@ -33,7 +35,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 form")
-    ap.add_argument("--cpu-steps", type=int, default=60, help="oracle steps of the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=400, help="oracle steps of the CPU sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -72,6 +74,26 @@ def time_solver(P, w, precision, steps, warmup, torch):
     _, diag = s.moments(check=False)
     s.close()
     return wall, ev, diag
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the same
+    counter reads for a plain copy of known size), or None when the kernel
+    source has changed since those counters were taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(PROFILE).read()
+        data = json.loads(re.search(r"```json\n(.*?)```", txt, flags=re.S).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != data.get("kernel_source_sha256_16"):
+        return None
+    return data.get(kernel, {}).get("traffic_bytes")
 
 
 def roofline(cells, dtype, ev_seconds, steps, traffic=None):
@@ -131,7 +153,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nr": w.nr, "ntheta": w.ntheta, "r": [w.r_min, w.r_max],
                    "cells": w.cells, "diag_every": 1, "parallelism": "single GPU"},
-        "roofline": roofline(w.cells, "f64", ev, a.steps),
+        "roofline": roofline(w.cells, "f64", ev, a.steps, measured_traffic("k_step_f64")),
         "hbm_frac_of_peak": None,
     }
     out["hbm_frac_of_peak"] = out["roofline"]["frac"]
@@ -142,7 +164,7 @@ def main():
         wall32, ev32, _ = time_solver(P, w32, P.PDBM_FP32, a.steps, a.warmup, torch)
         out["fp32"] = {"value": round(w32.cells * a.steps / wall32, 1), "unit": "cell-updates/s",
                        "ms_per_step": round(wall32 / a.steps * 1e3, 5), "speedup_vs_f64": round(wall / wall32, 3),
-                       "roofline": roofline(w32.cells, "f32", ev32, a.steps)}
+                       "roofline": roofline(w32.cells, "f32", ev32, a.steps, measured_traffic("k_step_f32"))}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out))
