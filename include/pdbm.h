@@ -202,6 +202,70 @@ int pdbm_write_f(pdbm_solver *s, const double *f, const double *lam, int64_t ste
 int pdbm_get_state(pdbm_solver *s, void *buf, size_t *bytes);
 int pdbm_set_state(pdbm_solver *s, const void *buf, size_t bytes);
 
+/* -------------------------------------------------------- packed batch -- */
+/* A fixed set of independent solves (each with its own grid, parameters and
+ * initial state; all of one precision) advanced together: one launch of the
+ * step kernel steps every member, and runs of `chunk_steps` launches are
+ * captured once in a HIP graph and replayed (chunk_steps = 0: plain
+ * launches).  Graphs need a stream other than the null stream: with
+ * stream = NULL and chunk_steps > 1 the batch creates a stream of its own.
+ * Each member's fields are bitwise those it would have alone in a batch of
+ * its own.  Errors as pdbm_create, for any member. */
+int pdbm_batch_create(int32_t n, const pdbm_params *params, const pdbm_ic *ics, int32_t chunk_steps, void *stream,
+                      pdbm_batch **out);
+void pdbm_batch_destroy(pdbm_batch *b);
+/* Enqueues nsteps steps of every member; returns without waiting. */
+int pdbm_batch_step(pdbm_batch *b, int64_t nsteps);
+int64_t pdbm_batch_step_count(const pdbm_batch *b, int32_t i);
+/* As pdbm_moments, for member i. */
+int pdbm_batch_moments(pdbm_batch *b, int32_t i, double *out, pdbm_diag *diag);
+
+/* ------------------------------------------------- continuous batching -- */
+/* A request server: submitted solves wait in a first-come-first-served queue
+ * and are admitted, between chunks of `chunk_steps` steps, while fewer than
+ * `max_slots` run and the device memory of the running ones (pdbm_state_bytes
+ * each) stays within `hbm_cap_bytes`.  All running solves advance together
+ * in packed, graph-captured launches on the server's stream (NULL: a stream
+ * of its own) driven by a scheduler thread; a solve leaves at the chunk
+ * boundary after it reaches its step count.  Submit and poll are
+ * thread-safe. */
+enum { PDBM_KEEP_FIELDS = 1 }; /* submit flag: keep the final fields for pdbm_poll */
+
+typedef struct pdbm_server_stats {
+    int64_t submitted, queued, running, done, failed;
+    int64_t steps_launched; /* chunks run x chunk_steps                      */
+    size_t hbm_in_use, hbm_cap;
+    double cell_updates;    /* grid cells x steps of the solves that finished */
+    double elapsed;         /* seconds since the server was created            */
+} pdbm_server_stats;
+
+int pdbm_server_create(size_t hbm_cap_bytes, int32_t max_slots, int32_t chunk_steps, void *stream,
+                       pdbm_server **out);
+/* Stops admitting, fails queued requests and those still running after the
+ * chunk in progress, joins the scheduler and frees everything. */
+void pdbm_server_destroy(pdbm_server *s);
+/* Queues a solve of `nsteps` steps and returns its id without waiting.
+ * PDBM_EINVAL / PDBM_ECFL as pdbm_validate; PDBM_ENOMEM if the solve alone
+ * exceeds the memory cap. */
+int pdbm_submit(pdbm_server *s, const pdbm_params *p, const pdbm_ic *ic, int64_t nsteps, uint32_t flags,
+                uint64_t *req_id);
+/* State of a request (PDBM_QUEUED / RUNNING / DONE / FAILED).  Returns
+ * PDBM_EAGAIN while it has not finished; once finished, fills `diag` (drift
+ * report of the final state) and, if it was submitted with
+ * PDBM_KEEP_FIELDS, `out` ([6][nr][ntheta] as pdbm_moments).  A request
+ * fails when its state turns non-finite or non-physical; the others are
+ * unaffected.  PDBM_ENOENT for an unknown id. */
+int pdbm_poll(pdbm_server *s, uint64_t req_id, int32_t *state, double *out, pdbm_diag *diag);
+/* Seconds since server creation at submit, admission and completion
+ * (-1 where it has not happened): times[3]. */
+int pdbm_request_times(pdbm_server *s, uint64_t req_id, double *times);
+/* Forgets a finished request and its kept fields. */
+int pdbm_release(pdbm_server *s, uint64_t req_id);
+/* Waits until no request is queued or running (timeout_s < 0: no limit);
+ * PDBM_EAGAIN on timeout. */
+int pdbm_server_wait(pdbm_server *s, double timeout_s);
+int pdbm_server_get_stats(pdbm_server *s, pdbm_server_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

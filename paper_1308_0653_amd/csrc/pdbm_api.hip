@@ -1,5 +1,6 @@
 // Host side of libpdbm: parameter validation, the moment-inversion matrix,
-// device memory layout, and the C ABI of one solve (include/pdbm.h).
+// the device memory of one solve, and the C ABI of a single solve
+// (include/pdbm.h).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -10,25 +11,13 @@
 #include <string>
 #include <vector>
 
-#include "pdbm_internal.h"
+#include "pdbm_host.h"
 
 using namespace pdbm;
 
 namespace {
 
 thread_local std::string g_err;
-
-int fail(int code, const std::string &msg)
-{
-    g_err = msg;
-    return code;
-}
-
-#define HIPCHK(call)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (call);                                                             \
-        if (e_ != hipSuccess) return fail(PDBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
 
 constexpr double SPEEDS[5] = {0.0, 1.5, 3.5, 7.5, 12.5};  // Sec. II.B
 constexpr int64_t MAX_CELLS = int64_t(1) << 24;
@@ -37,43 +26,39 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int pitch_of(int nt) { return nt <= 16 ? nt : (nt + 31) / 32 * 32; }
 
-// Device memory of one solve, in this order.
-struct Layout {
-    size_t f, lam, cs, desc, partials, counter, hist, total;
-    int pitch, nblocks;
-    size_t esz;
-};
+bool is_fin(double x) { return std::isfinite(x); }
 
-int blocks_of(const pdbm_params &p)
+}  // namespace
+
+#define HIPCHK PDBM_HIPCHK
+
+int pdbm::fail(int code, const std::string &msg)
 {
-    const int64_t cellb = ((int64_t)p.nr * p.ntheta + BLOCK - 1) / BLOCK;
-    const int rows = rows_per_wave(p.nr, p.ntheta, p.precision == PDBM_FP32);
-    const int64_t waves = (int64_t)((p.nr + rows - 1) / rows) * ((p.ntheta + STRIP - 1) / STRIP);
-    const int64_t stepb = (waves + BLOCK / 64 - 1) / (BLOCK / 64);
-    return (int)(cellb > stepb ? cellb : stepb);
+    g_err = msg;
+    return code;
 }
 
-Layout layout_of(const pdbm_params &p)
+Layout pdbm::layout_of(const pdbm_params &p, int rows)
 {
     Layout L;
     L.esz = p.precision == PDBM_FP32 ? sizeof(float) : sizeof(double);
     L.pitch = pitch_of(p.ntheta);
+    L.rows = rows;
+    L.nwaves = solve_waves(p.nr, p.ntheta, rows);
+    L.cblocks = cell_blocks(p.nr, p.ntheta);
     const size_t cells_p = (size_t)p.nr * L.pitch;
-    L.nblocks = blocks_of(p);
     L.f = align256((size_t)NQ * cells_p * L.esz);
     L.lam = align256(cells_p * sizeof(double));
     L.cs = align256((size_t)p.ntheta * sizeof(double2));
     L.desc = align256(sizeof(SolveDesc));
-    L.partials = align256((size_t)L.nblocks * 5 * sizeof(double));
-    L.counter = 256;
+    L.state = align256(sizeof(SolveState));
+    L.wpart = align256((size_t)L.nwaves * 5 * sizeof(double));
     L.hist = align256((size_t)(HIST_CAP + 1) * sizeof(pdbm_diag));
-    L.total = 2 * L.f + 2 * L.lam + L.cs + L.desc + L.partials + L.counter + L.hist;
+    L.cpart = align256((size_t)L.cblocks * 5 * sizeof(double));
+    L.counter = 256;
+    L.total = 2 * L.f + 2 * L.lam + L.cs + L.desc + L.state + L.wpart + L.hist + L.cpart + L.counter;
     return L;
 }
-
-bool is_fin(double x) { return std::isfinite(x); }
-
-}  // namespace
 
 // Rows per wavefront: just enough wavefronts for one resident wave of the
 // whole grid (256 CUs x 4 SIMDs x the step kernel's occupancy: 1 wavefront
@@ -186,7 +171,7 @@ int pdbm_state_bytes(const pdbm_params *p, size_t *bytes)
     if (p->nr < 1 || p->ntheta < 1 || (int64_t)p->nr * p->ntheta > MAX_CELLS ||
         (p->precision != PDBM_FP64 && p->precision != PDBM_FP32))
         return fail(PDBM_EINVAL, "bad grid or precision");
-    *bytes = layout_of(*p).total;
+    *bytes = layout_of(*p, rows_per_wave(p->nr, p->ntheta, p->precision == PDBM_FP32)).total;
     return PDBM_OK;
 }
 
@@ -218,72 +203,9 @@ int pdbm_fk_matrix(double *A)
 
 }  // extern "C"
 
-// ------------------------------------------------------------------ solver --
-struct pdbm_solver {
-    pdbm_params p;
-    hipStream_t st = nullptr;
-    Layout L;
-    bool fp32 = false, own = false;
-    char *ws = nullptr;
-    void *f[2] = {nullptr, nullptr};
-    double *lam[2] = {nullptr, nullptr};
-    double2 *cs = nullptr;
-    SolveDesc *ddesc = nullptr;  // device copy read by the step kernel
-    double *partials = nullptr;
-    unsigned *counter = nullptr;
-    pdbm_diag *hist = nullptr;  // [HIST_CAP] ring + 1 slot for pdbm_moments
-    int cur = 0;
-    int64_t step = 0, nrec = 0;
-    double A[16];
 
-    SolveDesc desc(int from) const
-    {
-        SolveDesc d;
-        std::memset(&d, 0, sizeof d);
-        d.f_in = f[from];
-        d.f_out = f[from ^ 1];
-        d.lam_in = lam[from];
-        d.lam_out = lam[from ^ 1];
-        d.cs = cs;
-        d.nr = p.nr;
-        d.nt = p.ntheta;
-        d.pitch = L.pitch;
-        d.sector = p.sector;
-        d.m = p.m;
-        d.n = p.n;
-        d.disc = p.r_min == 0.0;
-        d.reacts = (p.w1 > 0.0 || p.w2 > 0.0) ? 1 : 0;
-        d.rows = rows_per_wave(p.nr, p.ntheta, p.precision == PDBM_FP32);
-        d.plane = L.pitch;
-        d.rstride = (int64_t)NQ * L.pitch;
-        d.dr = (p.r_max - p.r_min) / p.nr;
-        d.dth = p.sector * M_PI / 4.0 / p.ntheta;
-        d.r_min = p.r_min;
-        d.dt_dr = p.dt / d.dr;
-        d.dt_dth = p.dt / d.dth;
-        d.omega = std::exp(-p.dt / p.tau);
-        d.w1 = p.w1;
-        d.w2 = p.w2;
-        d.Q = p.Q;
-        d.T_th = p.T_th;
-        d.dt = p.dt;
-        std::memcpy(d.A, A, sizeof A);
-        return d;
-    }
-    DiagCtl diag(pdbm_diag *out, bool on) const
-    {
-        DiagCtl c;
-        c.partials = partials;
-        c.counter = counter;
-        c.out = out;
-        c.step = step;
-        c.enabled = on ? 1 : 0;
-        c.pad = 0;
-        return c;
-    }
-};
-
-static int check_device()
+// ------------------------------------------------------------------- solve --
+int pdbm::check_device()
 {
     int dev = 0, n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(PDBM_ENOSYS, "no HIP device");
@@ -295,6 +217,134 @@ static int check_device()
     return PDBM_OK;
 }
 
+int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_t bytes, int rows, int64_t nsteps,
+                hipStream_t st)
+{
+    p = pp;
+    L = layout_of(p, rows);
+    fp32 = p.precision == PDBM_FP32;
+    if (workspace) {
+        if (bytes < L.total || ((uintptr_t)workspace & 255))
+            return fail(PDBM_ENOMEM, "workspace smaller than pdbm_state_bytes() or not 256-byte aligned");
+        ws = (char *)workspace;
+        own = false;
+    } else {
+        if (hipMalloc((void **)&ws, L.total) != hipSuccess) {
+            ws = nullptr;
+            return fail(PDBM_ENOMEM, "hipMalloc of the solve state failed");
+        }
+        own = true;
+    }
+    char *q = ws;
+    auto take = [&q](size_t n) {
+        char *r = q;
+        q += n;
+        return r;
+    };
+    std::memset(&hd, 0, sizeof hd);
+    hd.f[0] = take(L.f);
+    hd.f[1] = take(L.f);
+    hd.lam[0] = (double *)take(L.lam);
+    hd.lam[1] = (double *)take(L.lam);
+    hd.cs = (const double2 *)take(L.cs);
+    dd = (SolveDesc *)take(L.desc);
+    hd.state = (SolveState *)take(L.state);
+    hd.wpart = (double *)take(L.wpart);
+    hd.hist = (pdbm_diag *)take(L.hist);
+    cpart = (double *)take(L.cpart);
+    counter = (unsigned *)take(L.counter);
+
+    hd.nr = p.nr;
+    hd.nt = p.ntheta;
+    hd.pitch = L.pitch;
+    hd.sector = p.sector;
+    hd.m = p.m;
+    hd.n = p.n;
+    hd.disc = p.r_min == 0.0;
+    hd.reacts = (p.w1 > 0.0 || p.w2 > 0.0) ? 1 : 0;
+    hd.rows = rows;
+    hd.nwaves = L.nwaves;
+    hd.nstrip = (p.ntheta + STRIP - 1) / STRIP;
+    hd.diag_every = p.diag_every;
+    hd.plane = L.pitch;
+    hd.rstride = (int64_t)NQ * L.pitch;
+    hd.nsteps = nsteps;
+    hd.dr = (p.r_max - p.r_min) / p.nr;
+    hd.dth = p.sector * M_PI / 4.0 / p.ntheta;
+    hd.r_min = p.r_min;
+    hd.dt_dr = p.dt / hd.dr;
+    hd.dt_dth = p.dt / hd.dth;
+    hd.omega = std::exp(-p.dt / p.tau);
+    hd.w1 = p.w1;
+    hd.w2 = p.w2;
+    hd.Q = p.Q;
+    hd.T_th = p.T_th;
+    hd.dt = p.dt;
+    pdbm_fk_matrix(hd.A);
+
+    // theta table, description, zeroed counters, then the initial state.
+    // Host sources must outlive the copies: the caller synchronises st
+    // before returning to its own caller.
+    cs_host.resize(p.ntheta);
+    const double dth = hd.dth;
+    for (int j = 0; j < p.ntheta; ++j)
+        cs_host[j] = make_double2(std::cos((j + 0.5) * dth), std::sin((j + 0.5) * dth));
+    zero_state = SolveState{0, 0u, 0u};
+    HIPCHK(hipMemcpyAsync((void *)hd.cs, cs_host.data(), cs_host.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dd, &hd, sizeof hd, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(hd.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(counter, 0, sizeof(unsigned), st));
+    pdbm_ic uni;
+    if (!ic) {
+        std::memset(&uni, 0, sizeof uni);
+        for (double *t : {uni.inner, uni.outer}) {
+            t[0] = 1.0;
+            t[1] = 1.0;
+        }
+        ic = &uni;
+    }
+    HIPCHK(launch_init_ic(hd, 0, fp32, *ic, st));
+    step = 0;
+    rec_from = 0;
+    return PDBM_OK;
+}
+
+void Solve::release()
+{
+    if (own && ws) (void)hipFree(ws);
+    ws = nullptr;
+    own = false;
+}
+
+int Solve::set_step(int64_t s, hipStream_t st)
+{
+    zero_state = SolveState{s, 0u, 0u};
+    HIPCHK(hipMemcpyAsync(hd.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    step = s;
+    rec_from = s;
+    return PDBM_OK;
+}
+
+int Solve::moments(double *out, pdbm_diag *diag_dev, hipStream_t st) const
+{
+    DiagCtl c;
+    c.partials = cpart;
+    c.counter = counter;
+    c.out = diag_dev;
+    c.step = step;
+    c.enabled = 1;
+    c.pad = 0;
+    HIPCHK(launch_moments(hd, cur(), fp32, out, c, st));
+    return PDBM_OK;
+}
+
+// ------------------------------------------------------------ one solve ABI --
+struct pdbm_solver {
+    Solve s;
+    hipStream_t st = nullptr;
+};
+
 extern "C" {
 
 int pdbm_create(const pdbm_params *p, const pdbm_ic *ic, void *workspace, size_t workspace_bytes, void *stream,
@@ -305,185 +355,127 @@ int pdbm_create(const pdbm_params *p, const pdbm_ic *ic, void *workspace, size_t
     int rc = pdbm_validate(p, ic, nullptr);
     if (rc) return rc;
     if ((rc = check_device())) return rc;
-
-    pdbm_solver *s = new (std::nothrow) pdbm_solver;
-    if (!s) return fail(PDBM_ENOMEM, "host allocation failed");
-    s->p = *p;
-    s->st = (hipStream_t)stream;
-    s->L = layout_of(*p);
-    s->fp32 = p->precision == PDBM_FP32;
-    pdbm_fk_matrix(s->A);
-    if (workspace) {
-        if (workspace_bytes < s->L.total || ((uintptr_t)workspace & 255)) {
-            delete s;
-            return fail(PDBM_ENOMEM, "workspace smaller than pdbm_state_bytes() or not 256-byte aligned");
-        }
-        s->ws = (char *)workspace;
-    } else {
-        if (hipMalloc((void **)&s->ws, s->L.total) != hipSuccess) {
-            delete s;
-            return fail(PDBM_ENOMEM, "hipMalloc of the solve state failed");
-        }
-        s->own = true;
+    pdbm_solver *h = new (std::nothrow) pdbm_solver;
+    if (!h) return fail(PDBM_ENOMEM, "host allocation failed");
+    h->st = (hipStream_t)stream;
+    rc = h->s.init(*p, ic, workspace, workspace_bytes, rows_per_wave(p->nr, p->ntheta, p->precision == PDBM_FP32),
+                   INT64_MAX, h->st);
+    if (rc == PDBM_OK && hipStreamSynchronize(h->st) != hipSuccess) rc = fail(PDBM_EHIP, "initialisation failed");
+    if (rc) {
+        (void)hipStreamSynchronize(h->st);
+        h->s.release();
+        delete h;
+        return rc;
     }
-    char *q = s->ws;
-    s->f[0] = q;
-    q += s->L.f;
-    s->f[1] = q;
-    q += s->L.f;
-    s->lam[0] = (double *)q;
-    q += s->L.lam;
-    s->lam[1] = (double *)q;
-    q += s->L.lam;
-    s->cs = (double2 *)q;
-    q += s->L.cs;
-    s->ddesc = (SolveDesc *)q;
-    q += s->L.desc;
-    s->partials = (double *)q;
-    q += s->L.partials;
-    s->counter = (unsigned *)q;
-    q += s->L.counter;
-    s->hist = (pdbm_diag *)q;
-
-    // theta table and zeroed counter, then the initial state
-    std::vector<double2> cs(p->ntheta);
-    const double dth = p->sector * M_PI / 4.0 / p->ntheta;
-    for (int j = 0; j < p->ntheta; ++j) cs[j] = make_double2(std::cos((j + 0.5) * dth), std::sin((j + 0.5) * dth));
-    const unsigned zero = 0;
-    pdbm_ic uni;
-    if (!ic) {
-        std::memset(&uni, 0, sizeof uni);
-        for (double *t : {uni.inner, uni.outer}) {
-            t[0] = 1.0;
-            t[1] = 1.0;
-        }
-        ic = &uni;
-    }
-    hipError_t e = hipMemcpyAsync(s->cs, cs.data(), cs.size() * sizeof(double2), hipMemcpyHostToDevice, s->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->counter, &zero, sizeof zero, hipMemcpyHostToDevice, s->st);
-    const SolveDesc hd = s->desc(0);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->ddesc, &hd, sizeof hd, hipMemcpyHostToDevice, s->st);
-    if (e == hipSuccess) {
-        // the initial state goes to buffer 0: a desc reading 1 writes 0
-        e = launch_init_ic(s->desc(1), s->fp32, *ic, s->st);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-    if (e != hipSuccess) {
-        std::string m = std::string("initialisation failed: ") + hipGetErrorString(e);
-        pdbm_destroy(s);
-        return fail(PDBM_EHIP, m);
-    }
-    s->cur = 0;
-    *out = s;
+    *out = h;
     return PDBM_OK;
 }
 
-void pdbm_destroy(pdbm_solver *s)
+void pdbm_destroy(pdbm_solver *h)
 {
-    if (!s) return;
-    if (s->st || s->ws) (void)hipStreamSynchronize(s->st);
-    if (s->own && s->ws) (void)hipFree(s->ws);
-    delete s;
+    if (!h) return;
+    if (h->s.ws) (void)hipStreamSynchronize(h->st);
+    h->s.release();
+    delete h;
 }
 
-int pdbm_set_fields(pdbm_solver *s, const double *fields)
+int pdbm_set_fields(pdbm_solver *h, const double *fields)
 {
-    if (!s || !fields) return fail(PDBM_EINVAL, "NULL argument");
-    const size_t n = (size_t)5 * s->p.nr * s->p.ntheta;
-    // stage the fields in the idle f buffer (at least 132 bytes per cell)
-    double *stage = (double *)s->f[s->cur ^ 1];
-    HIPCHK(hipMemcpyAsync(stage, fields, n * sizeof(double), hipMemcpyHostToDevice, s->st));
-    HIPCHK(launch_init_fields(s->desc(s->cur ^ 1), s->fp32, stage, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
-    s->step = 0;
-    s->nrec = 0;
+    if (!h || !fields) return fail(PDBM_EINVAL, "NULL argument");
+    Solve &s = h->s;
+    const size_t n = (size_t)5 * s.p.nr * s.p.ntheta;
+    HIPCHK(hipStreamSynchronize(h->st));
+    // stage the fields in buffer 1 (at least 132 bytes per cell), build the
+    // state in buffer 0, and restart the step count
+    double *stage = (double *)s.hd.f[1];
+    HIPCHK(hipMemcpyAsync(stage, fields, n * sizeof(double), hipMemcpyHostToDevice, h->st));
+    HIPCHK(launch_init_fields(s.hd, 0, s.fp32, stage, h->st));
+    return s.set_step(0, h->st);
+}
+
+int pdbm_step(pdbm_solver *h, int64_t nsteps)
+{
+    if (!h || nsteps < 0) return fail(PDBM_EINVAL, "bad solver or step count");
+    Solve &s = h->s;
+    for (int64_t i = 0; i < nsteps; ++i) HIPCHK(launch_step(s.dd, nullptr, s.waves(), s.fp32, s.rot(), h->st));
+    s.step += nsteps;
     return PDBM_OK;
 }
 
-int pdbm_step(pdbm_solver *s, int64_t nsteps)
-{
-    if (!s || nsteps < 0) return fail(PDBM_EINVAL, "bad solver or step count");
-    for (int64_t i = 0; i < nsteps; ++i) {
-        const bool rec = s->p.diag_every > 0 && s->step % s->p.diag_every == 0;
-        pdbm_diag *slot = s->hist + (s->nrec % HIST_CAP);
-        HIPCHK(launch_step(s->desc(s->cur), s->ddesc, s->fp32, s->diag(slot, rec), s->st));
-        s->cur ^= 1;
-        s->step++;
-        if (rec) s->nrec++;
-    }
-    return PDBM_OK;
-}
+int64_t pdbm_step_count(const pdbm_solver *h) { return h ? h->s.step : -1; }
 
-int64_t pdbm_step_count(const pdbm_solver *s) { return s ? s->step : -1; }
-
-static int moments_into(pdbm_solver *s, double *dev_out)
+int pdbm_moments(pdbm_solver *h, double *out, pdbm_diag *diag)
 {
-    HIPCHK(launch_moments(s->desc(s->cur), s->fp32, dev_out, s->diag(s->hist + HIST_CAP, true), s->st));
-    return PDBM_OK;
-}
-
-int pdbm_moments(pdbm_solver *s, double *out, pdbm_diag *diag)
-{
-    if (!s) return fail(PDBM_EINVAL, "NULL solver");
-    double *stage = out ? (double *)s->f[s->cur ^ 1] : nullptr;  // idle buffer holds 6 doubles per cell
-    int rc = moments_into(s, stage);
+    if (!h) return fail(PDBM_EINVAL, "NULL solver");
+    Solve &s = h->s;
+    double *stage = out ? (double *)s.hd.f[s.cur() ^ 1] : nullptr;  // idle buffer holds 6 doubles per cell
+    pdbm_diag *dslot = s.hd.hist + HIST_CAP;
+    int rc = s.moments(stage, dslot, h->st);
     if (rc) return rc;
     pdbm_diag d;
     if (out)
-        HIPCHK(hipMemcpyAsync(out, stage, (size_t)6 * s->p.nr * s->p.ntheta * sizeof(double), hipMemcpyDeviceToHost,
-                              s->st));
-    HIPCHK(hipMemcpyAsync(&d, s->hist + HIST_CAP, sizeof d, hipMemcpyDeviceToHost, s->st));
-    HIPCHK(hipStreamSynchronize(s->st));
-    d.step = s->step;
+        HIPCHK(hipMemcpyAsync(out, stage, (size_t)6 * s.p.nr * s.p.ntheta * sizeof(double), hipMemcpyDeviceToHost,
+                              h->st));
+    HIPCHK(hipMemcpyAsync(&d, dslot, sizeof d, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    d.step = s.step;
     if (diag) *diag = d;
     if (d.n_nonfinite || d.n_nonphys) {
         char buf[160];
         std::snprintf(buf, sizeof buf, "step %lld: %lld non-finite cells, %lld cells with rho<=0 or T<=0",
-                      (long long)s->step, (long long)d.n_nonfinite, (long long)d.n_nonphys);
+                      (long long)s.step, (long long)d.n_nonfinite, (long long)d.n_nonphys);
         return fail(PDBM_ENONPHYS, buf);
     }
     return PDBM_OK;
 }
 
-int pdbm_moments_async(pdbm_solver *s, void *out_device)
+int pdbm_moments_async(pdbm_solver *h, void *out_device)
 {
-    if (!s || !out_device) return fail(PDBM_EINVAL, "NULL argument");
-    return moments_into(s, (double *)out_device);
+    if (!h || !out_device) return fail(PDBM_EINVAL, "NULL argument");
+    return h->s.moments((double *)out_device, h->s.hd.hist + HIST_CAP, h->st);
 }
 
-int pdbm_diag_history(pdbm_solver *s, pdbm_diag *out, int32_t cap, int32_t *n)
+int pdbm_diag_history(pdbm_solver *h, pdbm_diag *out, int32_t cap, int32_t *n)
 {
-    if (!s || !n || cap < 0 || (cap > 0 && !out)) return fail(PDBM_EINVAL, "bad argument");
-    HIPCHK(hipStreamSynchronize(s->st));
-    const int64_t have = s->nrec < HIST_CAP ? s->nrec : HIST_CAP;
-    const int64_t take = have < cap ? have : cap;
-    const int64_t first = s->nrec - take;  // oldest record returned
-    for (int64_t i = 0; i < take; ++i)
-        HIPCHK(hipMemcpy(out + i, s->hist + ((first + i) % HIST_CAP), sizeof(pdbm_diag), hipMemcpyDeviceToHost));
-    *n = (int32_t)take;
+    if (!h || !n || cap < 0 || (cap > 0 && !out)) return fail(PDBM_EINVAL, "bad argument");
+    Solve &s = h->s;
+    HIPCHK(hipStreamSynchronize(h->st));
+    *n = 0;
+    const int64_t de = s.p.diag_every;
+    if (de <= 0 || s.step <= s.rec_from) return PDBM_OK;
+    // records k cover steps k*de in [rec_from, step); the ring keeps HIST_CAP
+    int64_t k1 = (s.step - 1) / de + 1;          // one past the last record
+    int64_t k0 = (s.rec_from + de - 1) / de;     // first record since the reset
+    if (k1 - k0 > HIST_CAP) k0 = k1 - HIST_CAP;
+    if (k1 - k0 > cap) k0 = k1 - cap;
+    for (int64_t k = k0; k < k1; ++k)
+        HIPCHK(hipMemcpy(out + (k - k0), s.hd.hist + (k % HIST_CAP), sizeof(pdbm_diag), hipMemcpyDeviceToHost));
+    *n = (int32_t)(k1 - k0);
     return PDBM_OK;
 }
 
+}  // extern "C"
+
 // f on the device is [nr][NQ][pitch]; host arrays are [NQ][nr][ntheta].
-static hipError_t f_to_host(pdbm_solver *s, void *host)
+static hipError_t f_to_host(const Solve &s, void *host)
 {
-    const int nr = s->p.nr, nt = s->p.ntheta;
-    const size_t esz = s->L.esz, pitch = s->L.pitch;
+    const int nr = s.p.nr, nt = s.p.ntheta;
+    const size_t esz = s.L.esz, pitch = s.L.pitch;
     for (int q = 0; q < NQ; ++q) {
         hipError_t e = hipMemcpy2D((char *)host + (size_t)q * nr * nt * esz, nt * esz,
-                                   (const char *)s->f[s->cur] + q * pitch * esz, NQ * pitch * esz, nt * esz, nr,
+                                   (const char *)s.hd.f[s.cur()] + q * pitch * esz, NQ * pitch * esz, nt * esz, nr,
                                    hipMemcpyDeviceToHost);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-static hipError_t f_to_device(pdbm_solver *s, const void *host)
+static hipError_t f_to_device(const Solve &s, int buf, const void *host)
 {
-    const int nr = s->p.nr, nt = s->p.ntheta;
-    const size_t esz = s->L.esz, pitch = s->L.pitch;
+    const int nr = s.p.nr, nt = s.p.ntheta;
+    const size_t esz = s.L.esz, pitch = s.L.pitch;
     for (int q = 0; q < NQ; ++q) {
-        hipError_t e = hipMemcpy2D((char *)s->f[s->cur] + q * pitch * esz, NQ * pitch * esz,
+        hipError_t e = hipMemcpy2D((char *)s.hd.f[buf] + q * pitch * esz, NQ * pitch * esz,
                                    (const char *)host + (size_t)q * nr * nt * esz, nt * esz, nt * esz, nr,
                                    hipMemcpyHostToDevice);
         if (e != hipSuccess) return e;
@@ -491,14 +483,17 @@ static hipError_t f_to_device(pdbm_solver *s, const void *host)
     return hipSuccess;
 }
 
-int pdbm_read_f(pdbm_solver *s, double *f, double *lam)
+extern "C" {
+
+int pdbm_read_f(pdbm_solver *h, double *f, double *lam)
 {
-    if (!s) return fail(PDBM_EINVAL, "NULL solver");
-    const int nr = s->p.nr, nt = s->p.ntheta, pitch = s->L.pitch;
+    if (!h) return fail(PDBM_EINVAL, "NULL solver");
+    const Solve &s = h->s;
+    const int nr = s.p.nr, nt = s.p.ntheta, pitch = s.L.pitch;
     const size_t ncell = (size_t)nr * nt;
-    HIPCHK(hipStreamSynchronize(s->st));
+    HIPCHK(hipStreamSynchronize(h->st));
     if (f) {
-        if (s->fp32) {
+        if (s.fp32) {
             std::vector<float> tmp((size_t)NQ * ncell);
             HIPCHK(f_to_host(s, tmp.data()));
             for (size_t i = 0; i < tmp.size(); ++i) f[i] = tmp[i];
@@ -507,32 +502,38 @@ int pdbm_read_f(pdbm_solver *s, double *f, double *lam)
         }
     }
     if (lam)
-        HIPCHK(hipMemcpy2D(lam, nt * sizeof(double), s->lam[s->cur], pitch * sizeof(double), nt * sizeof(double), nr,
-                           hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy2D(lam, nt * sizeof(double), s.hd.lam[s.cur()], pitch * sizeof(double), nt * sizeof(double),
+                           nr, hipMemcpyDeviceToHost));
     return PDBM_OK;
 }
 
-int pdbm_write_f(pdbm_solver *s, const double *f, const double *lam, int64_t step)
+int pdbm_write_f(pdbm_solver *h, const double *f, const double *lam, int64_t step)
 {
-    if (!s || step < 0) return fail(PDBM_EINVAL, "bad argument");
-    const int nr = s->p.nr, nt = s->p.ntheta, pitch = s->L.pitch;
+    if (!h || step < 0) return fail(PDBM_EINVAL, "bad argument");
+    Solve &s = h->s;
+    const int nr = s.p.nr, nt = s.p.ntheta, pitch = s.L.pitch;
     const size_t ncell = (size_t)nr * nt;
-    HIPCHK(hipStreamSynchronize(s->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    const int cur = s.cur(), buf = (int)(step & 1);
+    if (cur != buf) {  // the state must end up in the buffer of the new step's parity
+        if (!f || !lam) {
+            HIPCHK(hipMemcpy(s.hd.f[buf], s.hd.f[cur], s.L.f, hipMemcpyDeviceToDevice));
+            HIPCHK(hipMemcpy(s.hd.lam[buf], s.hd.lam[cur], s.L.lam, hipMemcpyDeviceToDevice));
+        }
+    }
     if (f) {
-        if (s->fp32) {
+        if (s.fp32) {
             std::vector<float> tmp((size_t)NQ * ncell);
             for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)f[i];
-            HIPCHK(f_to_device(s, tmp.data()));
+            HIPCHK(f_to_device(s, buf, tmp.data()));
         } else {
-            HIPCHK(f_to_device(s, f));
+            HIPCHK(f_to_device(s, buf, f));
         }
     }
     if (lam)
-        HIPCHK(hipMemcpy2D(s->lam[s->cur], pitch * sizeof(double), lam, nt * sizeof(double), nt * sizeof(double), nr,
+        HIPCHK(hipMemcpy2D(s.hd.lam[buf], pitch * sizeof(double), lam, nt * sizeof(double), nt * sizeof(double), nr,
                            hipMemcpyHostToDevice));
-    s->step = step;
-    s->nrec = 0;
-    return PDBM_OK;
+    return s.set_step(step, h->st);
 }
 
 namespace {
@@ -544,46 +545,47 @@ struct BlobHeader {
 constexpr uint64_t BLOB_MAGIC = 0x3130455441545344ull;  // "DSTATE01"
 }  // namespace
 
-int pdbm_get_state(pdbm_solver *s, void *buf, size_t *bytes)
+int pdbm_get_state(pdbm_solver *h, void *buf, size_t *bytes)
 {
-    if (!s || !bytes) return fail(PDBM_EINVAL, "NULL argument");
-    const int nr = s->p.nr, nt = s->p.ntheta, pitch = s->L.pitch;
-    const size_t fb = (size_t)NQ * nr * nt * s->L.esz, lb = (size_t)nr * nt * sizeof(double);
+    if (!h || !bytes) return fail(PDBM_EINVAL, "NULL argument");
+    const Solve &s = h->s;
+    const int nr = s.p.nr, nt = s.p.ntheta, pitch = s.L.pitch;
+    const size_t fb = (size_t)NQ * nr * nt * s.L.esz, lb = (size_t)nr * nt * sizeof(double);
     const size_t need = sizeof(BlobHeader) + fb + lb;
     if (!buf) {
         *bytes = need;
         return PDBM_OK;
     }
     if (*bytes < need) return fail(PDBM_ENOMEM, "checkpoint buffer too small");
-    BlobHeader h{BLOB_MAGIC, 1, nr, nt, s->p.precision, s->step};
-    std::memcpy(buf, &h, sizeof h);
-    char *fdst = (char *)buf + sizeof h;
-    HIPCHK(hipStreamSynchronize(s->st));
+    BlobHeader hh{BLOB_MAGIC, 1, nr, nt, s.p.precision, s.step};
+    std::memcpy(buf, &hh, sizeof hh);
+    char *fdst = (char *)buf + sizeof hh;
+    HIPCHK(hipStreamSynchronize(h->st));
     HIPCHK(f_to_host(s, fdst));
-    HIPCHK(hipMemcpy2D(fdst + fb, nt * sizeof(double), s->lam[s->cur], pitch * sizeof(double), nt * sizeof(double),
+    HIPCHK(hipMemcpy2D(fdst + fb, nt * sizeof(double), s.hd.lam[s.cur()], pitch * sizeof(double), nt * sizeof(double),
                        nr, hipMemcpyDeviceToHost));
     *bytes = need;
     return PDBM_OK;
 }
 
-int pdbm_set_state(pdbm_solver *s, const void *buf, size_t bytes)
+int pdbm_set_state(pdbm_solver *h, const void *buf, size_t bytes)
 {
-    if (!s || !buf || bytes < sizeof(BlobHeader)) return fail(PDBM_EINVAL, "bad argument");
-    BlobHeader h;
-    std::memcpy(&h, buf, sizeof h);
-    const int nr = s->p.nr, nt = s->p.ntheta, pitch = s->L.pitch;
-    const size_t fb = (size_t)NQ * nr * nt * s->L.esz, lb = (size_t)nr * nt * sizeof(double);
-    if (h.magic != BLOB_MAGIC || h.version != 1 || h.nr != nr || h.ntheta != nt || h.precision != s->p.precision ||
-        h.step < 0 || bytes < sizeof h + fb + lb)
+    if (!h || !buf || bytes < sizeof(BlobHeader)) return fail(PDBM_EINVAL, "bad argument");
+    Solve &s = h->s;
+    BlobHeader hh;
+    std::memcpy(&hh, buf, sizeof hh);
+    const int nr = s.p.nr, nt = s.p.ntheta, pitch = s.L.pitch;
+    const size_t fb = (size_t)NQ * nr * nt * s.L.esz, lb = (size_t)nr * nt * sizeof(double);
+    if (hh.magic != BLOB_MAGIC || hh.version != 1 || hh.nr != nr || hh.ntheta != nt || hh.precision != s.p.precision ||
+        hh.step < 0 || bytes < sizeof hh + fb + lb)
         return fail(PDBM_EINVAL, "checkpoint does not match this solve");
-    const char *src = (const char *)buf + sizeof h;
-    HIPCHK(hipStreamSynchronize(s->st));
-    HIPCHK(f_to_device(s, src));
-    HIPCHK(hipMemcpy2D(s->lam[s->cur], pitch * sizeof(double), src + fb, nt * sizeof(double), nt * sizeof(double),
-                       nr, hipMemcpyHostToDevice));
-    s->step = h.step;
-    s->nrec = 0;
-    return PDBM_OK;
+    const char *src = (const char *)buf + sizeof hh;
+    const int b = (int)(hh.step & 1);
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(f_to_device(s, b, src));
+    HIPCHK(hipMemcpy2D(s.hd.lam[b], pitch * sizeof(double), src + fb, nt * sizeof(double), nt * sizeof(double), nr,
+                       hipMemcpyHostToDevice));
+    return s.set_step(hh.step, h->st);
 }
 
 }  // extern "C"

@@ -1,0 +1,70 @@
+// Host-side internals shared by the single-solve, batch and server parts of
+// libpdbm.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pdbm_internal.h"
+
+namespace pdbm {
+
+// Records `msg` as the calling thread's last error and returns `code`.
+int fail(int code, const std::string &msg);
+
+#define PDBM_HIPCHK(call)                                                                                      \
+    do {                                                                                                       \
+        hipError_t e_ = (call);                                                                                \
+        if (e_ != hipSuccess) return ::pdbm::fail(PDBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int DEFAULT_BATCH_ROWS = 16;  // rows per wavefront in packed launches
+
+// Device memory of one solve, in this order (all offsets 256-byte aligned).
+struct Layout {
+    size_t f, lam, cs, desc, state, wpart, hist, cpart, counter, total;
+    int pitch, rows, nwaves, cblocks;
+    size_t esz;
+};
+
+Layout layout_of(const pdbm_params &p, int rows);
+int check_device();
+
+// One solve resident on the GPU: its buffers, the description its kernels
+// read and a host mirror of its step counter.
+class Solve {
+  public:
+    pdbm_params p{};
+    Layout L{};
+    bool fp32 = false, own = false;
+    char *ws = nullptr;
+    SolveDesc hd{};           // host copy, pointers filled in
+    SolveDesc *dd = nullptr;  // device copy read by the step kernel
+    double *cpart = nullptr;  // moments-kernel reduction scratch
+    unsigned *counter = nullptr;
+    int64_t step = 0;      // steps taken (mirrors hd.state->step)
+    int64_t rec_from = 0;  // drift records are valid from this step on
+    std::vector<double2> cs_host;  // staging of uploads (kept until the next sync)
+    SolveState zero_state{};
+
+    // Lays out the solve in `workspace` (or a fresh allocation), uploads its
+    // description and enqueues its initial state on `st`.  `rows`: rows per
+    // wavefront; `nsteps`: step count after which the solve stops advancing.
+    int init(const pdbm_params &p, const pdbm_ic *ic, void *workspace, size_t bytes, int rows, int64_t nsteps,
+             hipStream_t st);
+    void release();  // frees an owned workspace (the stream must be idle)
+
+    int cur() const { return (int)(step & 1); }
+    int waves() const { return L.nwaves; }
+    bool rot() const { return p.sector != 8; }
+    // Sets the step count on host and device (stream must be idle).
+    int set_step(int64_t s, hipStream_t st);
+    // Fields [6][nr][ntheta] of the current state into device memory `out`
+    // and the drift report into `diag_dev` (both enqueued on st).
+    int moments(double *out, pdbm_diag *diag_dev, hipStream_t st) const;
+};
+
+}  // namespace pdbm

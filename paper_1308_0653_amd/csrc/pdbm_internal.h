@@ -15,20 +15,30 @@ constexpr int HIST_CAP = 4096;  // drift reports kept per solve
 constexpr int NXCD = 8;         // accelerator complex dies of an MI355X
 constexpr int STRIP = 62;       // theta columns stored per wavefront (64 lanes minus 2 halo lanes)
 
-// Everything a kernel needs to know about one solve.  Passed by value as a
-// kernel argument (one solve per launch) or read from a device table (packed
-// launches over many solves).
+// Mutable per-solve state in device memory, advanced by the step kernel
+// itself so that a captured graph of steps needs no host involvement.
+struct SolveState {
+    int64_t step;         // steps taken; the current f and lambda are buffer (step & 1)
+    uint32_t waves_done;  // wavefronts of the running step that have finished
+    uint32_t pad_;
+};
+
+// Everything a kernel needs to know about one solve.  The step kernel reads
+// it from device memory (one entry, or a table of entries for a packed
+// launch over many solves); the cell kernels take it by value.
 struct SolveDesc {
-    const void *f_in;  // [nr][NQ][pitch] of float or double: the 33 velocity rows of one r row are adjacent
-    void *f_out;
-    const double *lam_in;  // [nr][pitch]
-    double *lam_out;
+    void *f[2];         // [nr][NQ][pitch] float or double: the 33 velocity rows of one r row are adjacent
+    double *lam[2];     // [nr][pitch]
     const double2 *cs;  // [ntheta] (cos theta_j, sin theta_j)
+    SolveState *state;
+    double *wpart;      // [nwaves][5] per-wavefront drift partial sums of the running step
+    pdbm_diag *hist;    // [HIST_CAP] drift reports, record k for step k * diag_every
     int32_t nr, nt, pitch, sector;
-    int32_t m, n, disc, reacts;  // disc: r_min == 0; reacts: w1+w2 > 0
-    int32_t rows, pad_;          // rows marched by one wavefront per step
-    int64_t plane;               // elements between the rows of consecutive velocities (= pitch)
-    int64_t rstride;             // elements between consecutive r rows of f (= NQ * pitch)
+    int32_t m, n, disc, reacts;          // disc: r_min == 0; reacts: w1+w2 > 0
+    int32_t rows, nwaves, nstrip, diag_every;  // rows marched by one wavefront; its wavefronts
+    int64_t plane;    // elements between the rows of consecutive velocities (= pitch)
+    int64_t rstride;  // elements between consecutive r rows of f (= NQ * pitch)
+    int64_t nsteps;   // the solve stops advancing once it has taken this many steps
     double r_min, dr, dth;
     double dt_dr, dt_dth;  // dt/dr, dt/dtheta
     double omega;          // exp(-dt/tau)
@@ -36,35 +46,33 @@ struct SolveDesc {
     double A[16];  // F_k(T) = sum_n A[(k-1)*4+n-1] T^n
 };
 
-// The two f and lambda buffers of one step (they swap every step).
-struct StepBufs {
-    const void *f_in;
-    void *f_out;
-    const double *lam_in;
-    double *lam_out;
-};
-
-// Drift-report reduction state of one solve.
+// Block-level drift reduction of the cell kernels (moments).
 struct DiagCtl {
-    double *partials;    // [nblocks][5]
-    unsigned *counter;   // blocks finished, reset by the last one
-    pdbm_diag *out;      // where the final record goes
-    int64_t step;        // step count of the reduced state
+    double *partials;   // [nblocks][5]
+    unsigned *counter;  // blocks finished, reset by the last one
+    pdbm_diag *out;     // where the final record goes
+    int64_t step;       // step count of the reduced state
     int32_t enabled;
     int32_t pad;
 };
 
 // Kernel launchers (pdbm_kernels.hip).  All enqueue on `st` and return the
 // hipError_t of the launch.
-// The step kernel reads the solve's description from device memory
-// (dev_desc, a copy of d); d's buffer pointers give this step's buffers.
-hipError_t launch_step(const SolveDesc &d, const SolveDesc *dev_desc, bool fp32, const DiagCtl &dc, hipStream_t st);
-hipError_t launch_init_ic(const SolveDesc &d, bool fp32, const pdbm_ic &ic, hipStream_t st);
-hipError_t launch_init_fields(const SolveDesc &d, bool fp32, const double *fields, hipStream_t st);
-hipError_t launch_moments(const SolveDesc &d, bool fp32, double *out, const DiagCtl &dc, hipStream_t st);
-int cell_blocks(const SolveDesc &d);
-int step_blocks(const SolveDesc &d);
-// Rows per wavefront of the step kernel for an nr x nt grid.
+//
+// One step of every solve listed: `descs` is a device array of solve
+// descriptions; `tiles` maps each wavefront tile of the launch to (solve,
+// tile of that solve), or is NULL for a single solve (descs[0], tiles
+// 0..ntiles-1).  All solves share the precision; `rot` selects the variant
+// for sectors other than the full annulus.
+hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, bool fp32, bool rot, hipStream_t st);
+// Cell kernels on buffer `cur` of one solve.
+hipError_t launch_init_ic(const SolveDesc &d, int cur, bool fp32, const pdbm_ic &ic, hipStream_t st);
+hipError_t launch_init_fields(const SolveDesc &d, int cur, bool fp32, const double *fields, hipStream_t st);
+hipError_t launch_moments(const SolveDesc &d, int cur, bool fp32, double *out, const DiagCtl &dc, hipStream_t st);
+int cell_blocks(int nr, int nt);
+// Wavefront tiles of a solve marched `rows` rows at a time.
+int solve_waves(int nr, int nt, int rows);
+// Rows per wavefront of the step kernel for a solve that has the GPU to itself.
 int rows_per_wave(int nr, int nt, bool fp32);
 
 }  // namespace pdbm

@@ -235,6 +235,14 @@ typedef const __attribute__((address_space(4))) SolveDesc *DescPtr;
 typedef const SolveDesc *DescPtr;
 #endif
 
+// The two f and lambda buffers of one step (they swap every step).
+struct StepBufs {
+    const void *f_in;
+    void *f_out;
+    const double *lam_in;
+    double *lam_out;
+};
+
 // Raw buffer access to the f and lambda arrays: the lane's column offset is a
 // loop-invariant VGPR, the row and velocity-plane offsets a scalar register
 // (arrays stay below 4 GiB, which create() checks).
@@ -526,39 +534,94 @@ struct StepOcc {
     static constexpr int waves = sizeof(real) == 4 ? 2 : 1;
 };
 
-// One time step of a whole solve.  Wave w of the grid takes tile t = (its
-// block's XCD-ordered index) * 4 + w: row block t / nstrip, strip t % nstrip.
-template <typename real, bool ROT>
-__global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const SolveDesc *desc, StepBufs bufs, DiagCtl dc)
+// End of a wavefront's share of one step of one solve.  On a drift-report
+// step the wavefront's partial sums go to the solve's slot for it; the last
+// wavefront of the solve to finish adds all slots in a fixed order (the
+// report is the same whatever the finishing order), writes the record, and
+// advances the solve's step counter for the next launch.
+__device__ __forceinline__ void finish_wave(DescPtr dp, int lt, int64_t step, double red[5], bool diag)
 {
-    const DescPtr dp = (DescPtr)desc;
+    const int lane = threadIdx.x & 63;
+    if (diag) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double v = wave_sum(red[i]);
+            if (lane == 0) dp->wpart[5 * (size_t)lt + i] = v;
+        }
+    }
+    __threadfence();
+    unsigned done = 0;
+    if (lane == 0) done = atomicAdd(&dp->state->waves_done, 1u);
+    done = __builtin_amdgcn_readfirstlane(done);
+    if (done != (unsigned)(dp->nwaves - 1)) return;
+    __threadfence();
+    if (diag) {
+        double acc[5] = {0, 0, 0, 0, 0};
+        for (int w = lane; w < dp->nwaves; w += 64)
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                acc[i] += __hip_atomic_load(dp->wpart + 5 * (size_t)w + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i] = wave_sum(acc[i]);
+        if (lane == 0) {
+            pdbm_diag r;
+            r.step = step;
+            r.mass = acc[0];
+            r.energy = acc[1];
+            r.chem = acc[2];
+            r.n_nonfinite = (int64_t)acc[3];
+            r.n_nonphys = (int64_t)acc[4];
+            dp->hist[(step / dp->diag_every) % HIST_CAP] = r;
+        }
+    }
+    if (lane == 0) {
+        __hip_atomic_store(&dp->state->waves_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&dp->state->step, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// One time step of every solve of the launch.  Wavefront w of the grid takes
+// tile t = (its block's XCD-ordered index) * 4 + w, which the tile table maps
+// to (solve, tile of that solve); a solve's tile lt is row block lt / nstrip,
+// strip lt % nstrip.  Each wavefront works on its own: no block barriers.
+template <typename real, bool ROT>
+__global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const SolveDesc *descs, const uint2 *tiles,
+                                                                       int ntiles)
+{
     const int nb = gridDim.x;
     const int blk = xcd_tile(blockIdx.x, nb);
     // wave-uniform by construction; tell the compiler so that the row loop
     // and the offsets derived from it live in scalar registers
     const int t = __builtin_amdgcn_readfirstlane(blk * (BLOCK / 64) + (threadIdx.x >> 6));
-    const int rows = dp->rows, nr = dp->nr;
-    const int nrb = (nr + rows - 1) / rows;
-    const int nstrip = (dp->nt + STRIP - 1) / STRIP;
+    if (t >= ntiles) return;
+    int solve = 0, lt = t;
+    if (tiles) {
+        const uint2 e = tiles[t];
+        solve = __builtin_amdgcn_readfirstlane((int)e.x);
+        lt = __builtin_amdgcn_readfirstlane((int)e.y);
+    }
+    const DescPtr dp = (DescPtr)(descs + solve);
+    const int64_t step = dp->state->step;  // advanced only after all of this solve's wavefronts are done
+    if (step >= dp->nsteps) return;
+    const bool diag = dp->diag_every > 0 && step % dp->diag_every == 0;
+    const int cur = (int)(step & 1);
+    const StepBufs bufs{dp->f[cur], dp->f[cur ^ 1], dp->lam[cur], dp->lam[cur ^ 1]};
     __shared__ real prev[BLOCK / 64][NQ][64];
     double red[5] = {0, 0, 0, 0, 0};
-    const bool diag = dc.enabled != 0;
-    if (t < nrb * nstrip) {
-        // row-block major: the strips of one row block sit side by side in
-        // the same XCD and share their halo columns in its L2; odd row blocks
-        // march inward so that the rows bounding two blocks are read by both
-        // at the same time.
-        const int rb = t / nstrip, strip = t - rb * nstrip;
-        const int i0 = rb * rows;
-        const int i1 = min(i0 + rows, nr);
-        march<real, ROT>(dp, bufs, strip, i0, i1, (rb & 1) != 0, prev[threadIdx.x >> 6], red, diag);
-    }
-    if (diag) diag_reduce(dc, red, blk, nb);
+    // row-block major: the strips of one row block sit side by side in the
+    // same XCD and share their halo columns in its L2; odd row blocks march
+    // inward so that the rows bounding two blocks are read by both at once.
+    const int rows = dp->rows, nstrip = dp->nstrip;
+    const int rb = lt / nstrip, strip = lt - rb * nstrip;
+    const int i0 = rb * rows;
+    const int i1 = min(i0 + rows, dp->nr);
+    march<real, ROT>(dp, bufs, strip, i0, i1, (rb & 1) != 0, prev[threadIdx.x >> 6], red, diag);
+    finish_wave(dp, lt, step, red, diag);
 }
 
 // -------------------------------------------------------------- moments --
 template <typename real>
-__global__ __launch_bounds__(BLOCK) void k_moments(SolveDesc d, double *out, DiagCtl dc)
+__global__ __launch_bounds__(BLOCK) void k_moments(SolveDesc d, int cur, double *out, DiagCtl dc)
 {
     const int nb = gridDim.x;
     const int c = blockIdx.x * BLOCK + threadIdx.x;
@@ -567,7 +630,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(SolveDesc d, double *out, Dia
     if (c < ncell) {
         const int ir = c / d.nt;
         const int jt = c - ir * d.nt;
-        const real *fin = (const real *)d.f_in;
+        const real *fin = (const real *)d.f[cur];
         const int64_t idx = (int64_t)ir * d.pitch + jt;
         const int64_t fidx = (int64_t)ir * d.rstride + jt;
         real f[NQ];
@@ -579,7 +642,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(SolveDesc d, double *out, Dia
         const double ux = (double)(jx / rho), uy = (double)(jy / rho);
         const double T = (double)(e / rho - (real)0.5 * ((jx / rho) * (jx / rho) + (jy / rho) * (jy / rho)));
         const double2 cs = d.cs[jt];
-        const double lam = d.lam_in[idx];
+        const double lam = d.lam[cur][idx];
         if (out) {
             out[c] = rd;
             out[(size_t)ncell + c] = ux * cs.x + uy * cs.y;
@@ -614,20 +677,20 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
 }
 
 template <typename real>
-__device__ __forceinline__ void store_eq(const SolveDesc &d, int64_t idx, int jt, double rho, double T, double ur,
-                                         double ut)
+__device__ __forceinline__ void store_eq(const SolveDesc &d, int cur, int64_t idx, int jt, double rho, double T,
+                                         double ur, double ut)
 {
     const double2 cs = d.cs[jt];
     const double ux = ur * cs.x - ut * cs.y, uy = ur * cs.y + ut * cs.x;
     real f[NQ];
     equilibrium<real>(d.A, (real)rho, (real)ux, (real)uy, (real)T, f);
-    real *fo = (real *)d.f_out + (idx / d.pitch) * d.rstride + jt;
+    real *fo = (real *)d.f[cur] + (idx / d.pitch) * d.rstride + jt;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) fo[q * d.plane] = f[q];
 }
 
 template <typename real>
-__global__ __launch_bounds__(BLOCK) void k_init_ic(SolveDesc d, pdbm_ic ic)
+__global__ __launch_bounds__(BLOCK) void k_init_ic(SolveDesc d, int cur, pdbm_ic ic)
 {
     const int c = blockIdx.x * BLOCK + threadIdx.x;
     if (c >= d.nr * d.nt) return;
@@ -638,13 +701,13 @@ __global__ __launch_bounds__(BLOCK) void k_init_ic(SolveDesc d, pdbm_ic ic)
     const double *st = ri < ic.r_split ? ic.inner : ic.outer;
     const uint64_t h = splitmix64(ic.seed ^ ((uint64_t)c * 0x9E3779B97F4A7C15ull));
     const double p = noisy_pressure(st[0], st[1], ic.p_noise, h);
-    store_eq<real>(d, idx, jt, st[0], p / st[0], st[2], st[3]);
-    d.lam_out[idx] = st[4];
+    store_eq<real>(d, cur, idx, jt, st[0], p / st[0], st[2], st[3]);
+    d.lam[cur][idx] = st[4];
 }
 
 // fields: [5][nr][ntheta] = rho, T, u_r, u_theta, lambda
 template <typename real>
-__global__ __launch_bounds__(BLOCK) void k_init_fields(SolveDesc d, const double *fields)
+__global__ __launch_bounds__(BLOCK) void k_init_fields(SolveDesc d, int cur, const double *fields)
 {
     const int c = blockIdx.x * BLOCK + threadIdx.x;
     const int ncell = d.nr * d.nt;
@@ -652,68 +715,65 @@ __global__ __launch_bounds__(BLOCK) void k_init_fields(SolveDesc d, const double
     const int ir = c / d.nt;
     const int jt = c - ir * d.nt;
     const int64_t idx = (int64_t)ir * d.pitch + jt;
-    store_eq<real>(d, idx, jt, fields[c], fields[(size_t)ncell + c], fields[2 * (size_t)ncell + c],
+    store_eq<real>(d, cur, idx, jt, fields[c], fields[(size_t)ncell + c], fields[2 * (size_t)ncell + c],
                    fields[3 * (size_t)ncell + c]);
-    d.lam_out[idx] = fields[4 * (size_t)ncell + c];
+    d.lam[cur][idx] = fields[4 * (size_t)ncell + c];
 }
 
 }  // namespace
 
-int cell_blocks(const SolveDesc &d) { return (int)(((int64_t)d.nr * d.nt + BLOCK - 1) / BLOCK); }
+int cell_blocks(int nr, int nt) { return (int)(((int64_t)nr * nt + BLOCK - 1) / BLOCK); }
 
-int step_blocks(const SolveDesc &d)
+int solve_waves(int nr, int nt, int rows)
 {
-    const int64_t nrb = (d.nr + d.rows - 1) / d.rows;
-    const int64_t nstrip = (d.nt + STRIP - 1) / STRIP;
-    return (int)((nrb * nstrip + BLOCK / 64 - 1) / (BLOCK / 64));
+    return (int)((int64_t)((nr + rows - 1) / rows) * ((nt + STRIP - 1) / STRIP));
 }
 
-hipError_t launch_step(const SolveDesc &d, const SolveDesc *dev_desc, bool fp32, const DiagCtl &dc, hipStream_t st)
+hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, bool fp32, bool rot, hipStream_t st)
 {
-    const int nb = step_blocks(d);
-    const bool rot = d.sector != 8;
-    const StepBufs b{d.f_in, d.f_out, d.lam_in, d.lam_out};
+    const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
+    if (nb == 0) return hipSuccess;
     if (fp32) {
         if (rot)
-            hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, dev_desc, b, dc);
+            hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles);
         else
-            hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, dev_desc, b, dc);
+            hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles);
     } else {
         if (rot)
-            hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, dev_desc, b, dc);
+            hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles);
         else
-            hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, dev_desc, b, dc);
+            hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_moments(const SolveDesc &d, bool fp32, double *out, const DiagCtl &dc, hipStream_t st)
+hipError_t launch_moments(const SolveDesc &d, int cur, bool fp32, double *out, const DiagCtl &dc, hipStream_t st)
 {
-    const int nb = cell_blocks(d);
+    const int nb = cell_blocks(d.nr, d.nt);
     if (fp32)
-        hipLaunchKernelGGL(k_moments<float>, dim3(nb), dim3(BLOCK), 0, st, d, out, dc);
+        hipLaunchKernelGGL(k_moments<float>, dim3(nb), dim3(BLOCK), 0, st, d, cur, out, dc);
     else
-        hipLaunchKernelGGL(k_moments<double>, dim3(nb), dim3(BLOCK), 0, st, d, out, dc);
+        hipLaunchKernelGGL(k_moments<double>, dim3(nb), dim3(BLOCK), 0, st, d, cur, out, dc);
     return hipGetLastError();
 }
 
-hipError_t launch_init_ic(const SolveDesc &d, bool fp32, const pdbm_ic &ic, hipStream_t st)
+hipError_t launch_init_ic(const SolveDesc &d, int cur, bool fp32, const pdbm_ic &ic, hipStream_t st)
 {
-    const int nb = cell_blocks(d);
+    const int nb = cell_blocks(d.nr, d.nt);
     if (fp32)
-        hipLaunchKernelGGL(k_init_ic<float>, dim3(nb), dim3(BLOCK), 0, st, d, ic);
+        hipLaunchKernelGGL(k_init_ic<float>, dim3(nb), dim3(BLOCK), 0, st, d, cur, ic);
     else
-        hipLaunchKernelGGL(k_init_ic<double>, dim3(nb), dim3(BLOCK), 0, st, d, ic);
+        hipLaunchKernelGGL(k_init_ic<double>, dim3(nb), dim3(BLOCK), 0, st, d, cur, ic);
     return hipGetLastError();
 }
 
-hipError_t launch_init_fields(const SolveDesc &d, bool fp32, const double *fields, hipStream_t st)
+hipError_t launch_init_fields(const SolveDesc &d, int cur, bool fp32, const double *fields, hipStream_t st)
 {
-    const int nb = cell_blocks(d);
+    const int nb = cell_blocks(d.nr, d.nt);
     if (fp32)
-        hipLaunchKernelGGL(k_init_fields<float>, dim3(nb), dim3(BLOCK), 0, st, d, fields);
+        hipLaunchKernelGGL(k_init_fields<float>, dim3(nb), dim3(BLOCK), 0, st, d, cur, fields);
     else
-        hipLaunchKernelGGL(k_init_fields<double>, dim3(nb), dim3(BLOCK), 0, st, d, fields);
+        hipLaunchKernelGGL(k_init_fields<double>, dim3(nb), dim3(BLOCK), 0, st, d, cur, fields);
     return hipGetLastError();
 }
 

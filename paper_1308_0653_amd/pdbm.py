@@ -45,6 +45,18 @@ class pdbm_diag(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class pdbm_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("queued", C.c_int64), ("running", C.c_int64), ("done", C.c_int64),
+                ("failed", C.c_int64), ("steps_launched", C.c_int64), ("hbm_in_use", C.c_size_t),
+                ("hbm_cap", C.c_size_t), ("cell_updates", C.c_double), ("elapsed", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PDBM_KEEP_FIELDS = 1
+
+
 class PdbmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{msg} (code {code})")
@@ -89,6 +101,21 @@ def lib():
             "pdbm_write_f": (C.c_int, [vp, dp, dp, C.c_int64]),
             "pdbm_get_state": (C.c_int, [vp, vp, C.POINTER(C.c_size_t)]),
             "pdbm_set_state": (C.c_int, [vp, vp, C.c_size_t]),
+            "pdbm_batch_create": (C.c_int, [C.c_int32, C.POINTER(pdbm_params), C.POINTER(pdbm_ic), C.c_int32, vp,
+                                            C.POINTER(vp)]),
+            "pdbm_batch_destroy": (None, [vp]),
+            "pdbm_batch_step": (C.c_int, [vp, C.c_int64]),
+            "pdbm_batch_step_count": (C.c_int64, [vp, C.c_int32]),
+            "pdbm_batch_moments": (C.c_int, [vp, C.c_int32, dp, C.POINTER(pdbm_diag)]),
+            "pdbm_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.c_int32, vp, C.POINTER(vp)]),
+            "pdbm_server_destroy": (None, [vp]),
+            "pdbm_submit": (C.c_int, [vp, C.POINTER(pdbm_params), C.POINTER(pdbm_ic), C.c_int64, C.c_uint32,
+                                      C.POINTER(C.c_uint64)]),
+            "pdbm_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(C.c_int32), dp, C.POINTER(pdbm_diag)]),
+            "pdbm_request_times": (C.c_int, [vp, C.c_uint64, dp]),
+            "pdbm_release": (C.c_int, [vp, C.c_uint64]),
+            "pdbm_server_wait": (C.c_int, [vp, C.c_double]),
+            "pdbm_server_get_stats": (C.c_int, [vp, C.POINTER(pdbm_server_stats)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -261,3 +288,117 @@ class Solver:
         _check(self.L.pdbm_set_state(self.h, buf, len(blob)))
 
     set_state = pdbm_set_state
+
+
+class Batch:
+    """Handle of a packed batch of independent solves (pdbm_batch_*)."""
+
+    def __init__(self, params: list, ics: list | None = None, chunk_steps: int = 0, stream=None):
+        self.L = lib()
+        n = len(params)
+        self.shapes = [(p.nr, p.ntheta) for p in params]
+        P = (pdbm_params * n)(*params)
+        I = (pdbm_ic * n)(*ics) if ics is not None else None
+        self.h = C.c_void_p()
+        _check(self.L.pdbm_batch_create(n, P, I, int(chunk_steps), C.c_void_p(_stream_handle(stream)),
+                                        C.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            self.L.pdbm_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pdbm_batch_step(self, nsteps: int = 1):
+        _check(self.L.pdbm_batch_step(self.h, int(nsteps)))
+
+    step = pdbm_batch_step
+
+    def step_count(self, i: int) -> int:
+        return self.L.pdbm_batch_step_count(self.h, int(i))
+
+    def pdbm_batch_moments(self, i: int, check: bool = True):
+        nr, nt = self.shapes[i]
+        out = np.empty((6, nr, nt))
+        d = pdbm_diag()
+        rc = self.L.pdbm_batch_moments(self.h, int(i), _dptr(out), C.byref(d))
+        if rc != PDBM_ENONPHYS or check:
+            _check(rc)
+        return out, d.as_dict()
+
+    moments = pdbm_batch_moments
+
+
+class Server:
+    """Handle of a continuous-batching request server (pdbm_server_*)."""
+
+    def __init__(self, hbm_cap_bytes: int, max_slots: int = 64, chunk_steps: int = 50, stream=None):
+        self.L = lib()
+        self.h = C.c_void_p()
+        self.shapes = {}
+        _check(self.L.pdbm_server_create(int(hbm_cap_bytes), int(max_slots), int(chunk_steps),
+                                         C.c_void_p(_stream_handle(stream)), C.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            self.L.pdbm_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pdbm_submit(self, params: pdbm_params, ic: pdbm_ic, nsteps: int, keep_fields: bool = False) -> int:
+        rid = C.c_uint64(0)
+        _check(self.L.pdbm_submit(self.h, C.byref(params), C.byref(ic), int(nsteps),
+                                  PDBM_KEEP_FIELDS if keep_fields else 0, C.byref(rid)))
+        self.shapes[rid.value] = (params.nr, params.ntheta, keep_fields)
+        return rid.value
+
+    submit = pdbm_submit
+
+    def pdbm_poll(self, rid: int, fields: bool = False):
+        """Returns (state, fields or None, drift report or None); state is
+        PDBM_QUEUED / RUNNING / DONE / FAILED."""
+        st = C.c_int32(-1)
+        d = pdbm_diag()
+        out = None
+        nr, nt, kept = self.shapes.get(rid, (0, 0, False))
+        if fields and kept:
+            out = np.empty((6, nr, nt))
+        rc = self.L.pdbm_poll(self.h, C.c_uint64(rid), C.byref(st), _dptr(out) if out is not None else None,
+                              C.byref(d))
+        if rc == PDBM_EAGAIN:
+            return st.value, None, None
+        _check(rc)
+        return st.value, out, d.as_dict()
+
+    poll = pdbm_poll
+
+    def times(self, rid: int):
+        t = np.zeros(3)
+        _check(self.L.pdbm_request_times(self.h, C.c_uint64(rid), _dptr(t)))
+        return t
+
+    def release(self, rid: int):
+        _check(self.L.pdbm_release(self.h, C.c_uint64(rid)))
+        self.shapes.pop(rid, None)
+
+    def wait(self, timeout_s: float = -1.0) -> bool:
+        rc = self.L.pdbm_server_wait(self.h, float(timeout_s))
+        if rc == PDBM_EAGAIN:
+            return False
+        _check(rc)
+        return True
+
+    def stats(self) -> dict:
+        st = pdbm_server_stats()
+        _check(self.L.pdbm_server_get_stats(self.h, C.byref(st)))
+        return st.as_dict()

@@ -1,0 +1,189 @@
+"""Packed batches and the continuous-batching server on the GPU.
+
+A solve's fields must be bitwise the same alone and in any mix (members
+never read each other's data), its drift report equal to rounding, and each
+result must match the CPU oracle."""
+import time
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_0653_amd import pdbm as P
+from paper_1308_0653_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(w, precision, diag_every=0):
+    return P.make_params(**w.params_kw(), precision=precision, diag_every=diag_every)
+
+
+def _small_sweep(n, seed=0, nsteps=60):
+    """A few solves with the sweep's parameter ranges on small grids."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        nr, nt = int(rng.integers(24, 90)), int(rng.integers(20, 140))
+        w = replace(W.batch_sweep(count=i + 1, nsteps=nsteps)[i], nr=nr, ntheta=nt)
+        out.append(w)
+    return out
+
+
+def _oracle_fields(w, nsteps):
+    o = O.Solver(O.make_params(**w.params_kw()))
+    o.init_ic(**w.ic_kw())
+    o.step(nsteps)
+    return o.fields()
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("chunk", [0, 7])
+def test_batch_members_match_single_solves_and_oracle(chunk):
+    ws = _small_sweep(4, seed=1)
+    params = [_params(w, P.PDBM_FP64, diag_every=5) for w in ws]
+    ics = [P.make_ic(**w.ic_kw()) for w in ws]
+    b = P.Batch(params, ics, chunk_steps=chunk)
+    b.step(30)
+    for i, w in enumerate(ws):
+        assert b.step_count(i) == 30
+        F, d = b.moments(i)
+        solo = P.Solver(params[i], ics[i])
+        solo.step(30)
+        Fs, ds = solo.moments()
+        assert np.array_equal(F, Fs), i
+        for k in ("mass", "energy", "chem"):
+            assert abs(d[k] - ds[k]) <= 1e-14 * abs(ds[k])
+        R = _oracle_fields(w, 30)
+        for k in (0, 3, 5):
+            assert _rel(F[k], R[k]) < 1e-10, (i, k)
+
+
+def test_batch_graph_replay_equals_plain_launches():
+    ws = _small_sweep(3, seed=2)
+    params = [_params(w, P.PDBM_FP32, diag_every=4) for w in ws]
+    ics = [P.make_ic(**w.ic_kw()) for w in ws]
+    a = P.Batch(params, ics, chunk_steps=6)
+    b = P.Batch(params, ics, chunk_steps=0)
+    for n in (13, 6, 1, 12):  # whole chunks and remainders
+        a.step(n)
+        b.step(n)
+    for i in range(len(ws)):
+        Fa, da = a.moments(i)
+        Fb, db = b.moments(i)
+        assert np.array_equal(Fa, Fb)
+        assert da == db
+
+
+def test_batch_member_alone_equals_in_mix_fp32():
+    ws = _small_sweep(5, seed=3)
+    params = [_params(w, P.PDBM_FP32) for w in ws]
+    ics = [P.make_ic(**w.ic_kw()) for w in ws]
+    mix = P.Batch(params, ics, chunk_steps=10)
+    mix.step(40)
+    for i in (0, 3):
+        alone = P.Batch([params[i]], [ics[i]], chunk_steps=10)
+        alone.step(40)
+        Fm, dm = mix.moments(i)
+        Fa, da = alone.moments(0)
+        assert np.array_equal(Fm, Fa)
+        assert dm == da
+
+
+def _wait_all(srv, ids, timeout=60.0):
+    assert srv.wait(timeout), srv.stats()
+    return {rid: srv.poll(rid, fields=True) for rid in ids}
+
+
+def test_server_results_equal_solo_runs():
+    ws = _small_sweep(6, seed=4, nsteps=40)
+    srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=3, chunk_steps=8)
+    ids = []
+    for k, w in enumerate(ws):
+        prec = P.PDBM_FP64 if k % 2 else P.PDBM_FP32
+        ids.append((srv.submit(_params(w, prec), P.make_ic(**w.ic_kw()), nsteps=w.nsteps + 7 * k,
+                               keep_fields=True), w, prec, w.nsteps + 7 * k))
+    res = _wait_all(srv, [i for i, *_ in ids])
+    for rid, w, prec, n in ids:
+        state, F, d = res[rid]
+        assert state == P.PDBM_DONE
+        solo = P.Batch([_params(w, prec)], [P.make_ic(**w.ic_kw())], chunk_steps=0)
+        solo.step(n)
+        Fs, ds = solo.moments(0)
+        assert np.array_equal(F, Fs), rid
+        t = srv.times(rid)
+        assert 0 <= t[0] <= t[1] <= t[2]
+    st = srv.stats()
+    assert st["done"] == len(ws) and st["failed"] == 0 and st["queued"] == 0 and st["running"] == 0
+    srv.close()
+
+
+def test_server_admission_by_slots_and_memory():
+    w0 = _small_sweep(1, seed=5, nsteps=30)[0]
+    ws = [replace(w0, seed=k) for k in range(5)]  # same size, different noise
+    p0 = _params(ws[0], P.PDBM_FP32)
+    need = P.pdbm_state_bytes(p0)
+    # memory for only one running solve at a time
+    srv = P.Server(hbm_cap_bytes=need + need // 2, max_slots=8, chunk_steps=5)
+    ids = [srv.submit(_params(w, P.PDBM_FP32), P.make_ic(**w.ic_kw()), nsteps=30) for w in ws]
+    assert srv.wait(60.0)
+    spans = sorted(tuple(srv.times(i)[1:]) for i in ids)
+    for (a1, d1), (a2, d2) in zip(spans, spans[1:]):
+        assert a2 >= d1 - 1e-9  # admitted only after the previous one left
+    assert srv.stats()["done"] == len(ws)
+    # and by slots: two at a time
+    srv2 = P.Server(hbm_cap_bytes=8 << 30, max_slots=2, chunk_steps=5)
+    ids = [srv2.submit(_params(w, P.PDBM_FP32), P.make_ic(**w.ic_kw()), nsteps=30) for w in ws]
+    assert srv2.wait(60.0)
+    spans = [tuple(srv2.times(i)[1:]) for i in ids]
+    for t in np.linspace(0, max(d for _, d in spans), 200):
+        assert sum(a <= t < d for a, d in spans) <= 2
+    srv2.close()
+    # a solve that can never fit is refused at submission
+    small = P.Server(hbm_cap_bytes=1 << 20, max_slots=2, chunk_steps=5)
+    with pytest.raises(P.PdbmError) as e:
+        small.submit(p0, P.make_ic(**ws[0].ic_kw()), 10)
+    assert e.value.code == P.PDBM_ENOMEM
+    with pytest.raises(P.PdbmError) as e:
+        small.poll(12345)
+    assert e.value.code == P.PDBM_ENOENT
+    small.close()
+    srv.close()
+
+
+def test_server_failure_is_isolated():
+    """A solve whose state blows up (burnt gas at T = 20 is outside the
+    model's stable range) fails alone; the others are bitwise unaffected."""
+    good = _small_sweep(3, seed=6, nsteps=60)
+    bad = W.Workload("unstable", 48, 1024, 0.05, 0.2, dt=1e-5, tau=2e-5, w1=2.0, w2=2.0, m=2, n=2, Q=1.0,
+                     T_th=1.1, r_split=0.1, inner=(1.5, 20.0, 0.0, 0.0, 1.0), outer=(1.0, 1.0, 0.0, 0.0, 0.0),
+                     p_noise=1e-6, seed=0, nsteps=100)
+    srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=8, chunk_steps=10)
+    gid = [srv.submit(_params(w, P.PDBM_FP32), P.make_ic(**w.ic_kw()), w.nsteps, keep_fields=True) for w in good]
+    bid = srv.submit(_params(bad, P.PDBM_FP32), P.make_ic(**bad.ic_kw()), bad.nsteps)
+    assert srv.wait(60.0)
+    state, _, d = srv.poll(bid)
+    assert state == P.PDBM_FAILED and (d["n_nonfinite"] > 0 or d["n_nonphys"] > 0)
+    for rid, w in zip(gid, good):
+        state, F, _ = srv.poll(rid, fields=True)
+        assert state == P.PDBM_DONE
+        solo = P.Batch([_params(w, P.PDBM_FP32)], [P.make_ic(**w.ic_kw())])
+        solo.step(w.nsteps)
+        assert np.array_equal(F, solo.moments(0)[0])
+    assert srv.stats()["failed"] == 1
+    srv.close()
+
+
+def test_server_shutdown_with_pending_work():
+    w = _small_sweep(1, seed=7)[0]
+    srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=1, chunk_steps=5)
+    ids = [srv.submit(_params(w, P.PDBM_FP32), P.make_ic(**w.ic_kw()), 100000) for _ in range(3)]
+    time.sleep(0.2)
+    t0 = time.perf_counter()
+    srv.close()  # must not wait for the 100000-step solves
+    assert time.perf_counter() - t0 < 10.0
+    assert ids
