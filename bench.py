@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -36,6 +38,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 form")
     ap.add_argument("--cpu-steps", type=int, default=400, help="oracle steps of the CPU sample")
+    ap.add_argument("--no-serving", action="store_true", help="skip the packed-batch and serving measurements")
+    ap.add_argument("--batch-solves", type=int, default=256, help="solves of the packed parameter sweep")
+    ap.add_argument("--batch-steps", type=int, default=500, help="steps of each solve of the sweep")
+    ap.add_argument("--serving-requests", type=int, default=120,
+                    help="requests of the Poisson serving stream (1000 in the full workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -104,6 +111,95 @@ def roofline(cells, dtype, ev_seconds, steps, traffic=None):
             "bytes_per_launch": per_launch, "kernel": "k_step", "avg_launch_us": round(ev_seconds / steps * 1e6, 2)}
 
 
+def packed_sweep(P, W, torch, count, nsteps):
+    """Independent float32 solves of the parameter sweep advanced together in
+    packed, graph-captured launches (chunks of 50 steps)."""
+    ws = W.batch_sweep(count=count, nsteps=nsteps)
+    params = [P.make_params(**w.params_kw(), precision=P.PDBM_FP32) for w in ws]
+    ics = [P.make_ic(**w.ic_kw()) for w in ws]
+    stream = torch.cuda.Stream()
+    b = P.Batch(params, ics, chunk_steps=50, stream=stream)
+    b.step(50)  # warm-up (captures the graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(nsteps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cells = sum(w.cells for w in ws)
+    failed = 0
+    for i in range(len(ws)):
+        _, d = b.moments(i, check=False)
+        failed += int(d["n_nonfinite"] > 0 or d["n_nonphys"] > 0)
+    b.close()
+    rate = cells * nsteps / wall
+    return {"workload": f"sweep{count}_fp32", "solves": count, "steps": nsteps, "cells": cells,
+            "value": round(rate, 1), "unit": "cell-updates/s", "wall_s": round(wall, 4),
+            "hbm_frac": round(rate * BYTES_PER_CELL["f32"] / (HBM_PEAK_GBS * 1e9), 4),
+            "latency_s": round(wall, 4), "failed": failed}
+
+
+def serving_stream(P, W, torch, nreq, packed_rate):
+    """Poisson arrivals served by the continuous-batching server (float32,
+    chunks of 25 steps, 200 GB cap), against the plain float64 path running
+    the same requests one at a time in arrival order."""
+    import threading
+    mean_work = W.mean_work_serving()
+    rate = 0.8 * packed_rate / mean_work  # offered load 0.8 of the packed throughput
+    stream = W.serving_stream(count=nreq, rate=rate)
+    srv = P.Server(hbm_cap_bytes=200 * 10**9, max_slots=64, chunk_steps=25)
+    ids = [None] * len(stream)
+    t_start = time.perf_counter()
+
+    def feeder():
+        for k, (t_arr, w) in enumerate(stream):
+            delay = t_arr - (time.perf_counter() - t_start)
+            if delay > 0:
+                time.sleep(delay)
+            ids[k] = srv.submit(P.make_params(**w.params_kw(), precision=P.PDBM_FP32), P.make_ic(**w.ic_kw()),
+                                w.nsteps)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    srv.wait(-1)
+    wall = time.perf_counter() - t_start
+    lat = []
+    failed = 0
+    for rid in ids:
+        t = srv.times(rid)
+        lat.append(t[2] - t[0])
+        failed += int(srv.poll(rid)[0] != P.PDBM_DONE)
+    st = srv.stats()
+    srv.close()
+    work = sum(w.cells * w.nsteps for _, w in stream)
+    served = {"requests": nreq, "offered_rate_per_s": round(rate, 3), "wall_s": round(wall, 3),
+              "value": round(work / wall, 1), "unit": "cell-updates/s",
+              "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+              "p99_latency_s": round(float(np.percentile(lat, 99)), 4), "failed": failed,
+              "steps_launched": st["steps_launched"]}
+    # the plain float64 path, one solve at a time in arrival order (FIFO):
+    # each solve's own time on the GPU, queued behind the ones before it
+    busy_until, lat64, gpu_time = 0.0, [], 0.0
+    torch.cuda.synchronize()
+    for t_arr, w in stream:
+        s = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64), P.make_ic(**w.ic_kw()),
+                     stream=torch.cuda.current_stream())
+        t0 = time.perf_counter()
+        s.step(w.nsteps)
+        s.moments(check=False)
+        dt = time.perf_counter() - t0
+        s.close()
+        gpu_time += dt
+        start = max(t_arr, busy_until)
+        busy_until = start + dt
+        lat64.append(busy_until - t_arr)
+    serial = {"value": round(work / gpu_time, 1), "unit": "cell-updates/s",
+              "p50_latency_s": round(float(np.percentile(lat64, 50)), 4),
+              "p99_latency_s": round(float(np.percentile(lat64, 99)), 4),
+              "busy_s": round(gpu_time, 3)}
+    return served, serial
+
+
 def cpu_baseline(w, steps):
     """The CPU oracle, as it stands, on a bounded sample of the same
     workload: the full grid for `steps` steps."""
@@ -165,6 +261,12 @@ def main():
         out["fp32"] = {"value": round(w32.cells * a.steps / wall32, 1), "unit": "cell-updates/s",
                        "ms_per_step": round(wall32 / a.steps * 1e3, 5), "speedup_vs_f64": round(wall / wall32, 3),
                        "roofline": roofline(w32.cells, "f32", ev32, a.steps, measured_traffic("k_step_f32"))}
+    if not a.no_serving:
+        sweep = packed_sweep(P, W, torch, a.batch_solves, a.batch_steps)
+        out["packed_sweep"] = sweep
+        served, serial = serving_stream(P, W, torch, a.serving_requests, sweep["value"])
+        out["serving"] = {"served_fp32": served, "serial_fp64": serial,
+                          "workload": f"poisson{a.serving_requests}_logU"}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out))

@@ -203,11 +203,13 @@ int pdbm_get_state(pdbm_solver *s, void *buf, size_t *bytes);
 int pdbm_set_state(pdbm_solver *s, const void *buf, size_t bytes);
 
 /* -------------------------------------------------------- packed batch -- */
+enum { PDBM_MAX_CHUNK = 64 }; /* longest run of launches captured in one graph */
+
 /* A fixed set of independent solves (each with its own grid, parameters and
  * initial state; all of one precision) advanced together: one launch of the
  * step kernel steps every member, and runs of `chunk_steps` launches are
  * captured once in a HIP graph and replayed (chunk_steps = 0: plain
- * launches).  Graphs need a stream other than the null stream: with
+ * launches; at most PDBM_MAX_CHUNK, else PDBM_EINVAL).  Graphs need a stream other than the null stream: with
  * stream = NULL and chunk_steps > 1 the batch creates a stream of its own.
  * Each member's fields are bitwise those it would have alone in a batch of
  * its own.  Errors as pdbm_create, for any member. */
@@ -222,7 +224,8 @@ int pdbm_batch_moments(pdbm_batch *b, int32_t i, double *out, pdbm_diag *diag);
 
 /* ------------------------------------------------- continuous batching -- */
 /* A request server: submitted solves wait in a first-come-first-served queue
- * and are admitted, between chunks of `chunk_steps` steps, while fewer than
+ * and are admitted, between chunks of `chunk_steps` (1 to PDBM_MAX_CHUNK)
+ * steps, while fewer than
  * `max_slots` run and the device memory of the running ones (pdbm_state_bytes
  * each) stays within `hbm_cap_bytes`.  All running solves advance together
  * in packed, graph-captured launches on the server's stream (NULL: a stream

@@ -52,7 +52,7 @@ Layout pdbm::layout_of(const pdbm_params &p, int rows)
     L.cs = align256((size_t)p.ntheta * sizeof(double2));
     L.desc = align256(sizeof(SolveDesc));
     L.state = align256(sizeof(SolveState));
-    L.wpart = align256((size_t)L.nwaves * 5 * sizeof(double));
+    L.wpart = align256((size_t)PART_RING * L.nwaves * 5 * sizeof(double));
     L.hist = align256((size_t)(HIST_CAP + 1) * sizeof(pdbm_diag));
     L.cpart = align256((size_t)L.cblocks * 5 * sizeof(double));
     L.counter = 256;
@@ -289,7 +289,7 @@ int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_
     const double dth = hd.dth;
     for (int j = 0; j < p.ntheta; ++j)
         cs_host[j] = make_double2(std::cos((j + 0.5) * dth), std::sin((j + 0.5) * dth));
-    zero_state = SolveState{0, 0u, 0u};
+    zero_state = SolveState{0};
     HIPCHK(hipMemcpyAsync((void *)hd.cs, cs_host.data(), cs_host.size() * sizeof(double2), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(dd, &hd, sizeof hd, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(hd.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice, st));
@@ -306,6 +306,7 @@ int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_
     HIPCHK(launch_init_ic(hd, 0, fp32, *ic, st));
     step = 0;
     rec_from = 0;
+    red_to = 0;
     return PDBM_OK;
 }
 
@@ -318,11 +319,19 @@ void Solve::release()
 
 int Solve::set_step(int64_t s, hipStream_t st)
 {
-    zero_state = SolveState{s, 0u, 0u};
+    zero_state = SolveState{s};
     HIPCHK(hipMemcpyAsync(hd.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     step = s;
     rec_from = s;
+    red_to = s;
+    return PDBM_OK;
+}
+
+int Solve::reduce_records(hipStream_t st)
+{
+    if (step > red_to) HIPCHK(launch_records(dd, 1, nullptr, red_to, step, st));
+    red_to = step;
     return PDBM_OK;
 }
 
@@ -397,8 +406,13 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
 {
     if (!h || nsteps < 0) return fail(PDBM_EINVAL, "bad solver or step count");
     Solve &s = h->s;
-    for (int64_t i = 0; i < nsteps; ++i) HIPCHK(launch_step(s.dd, nullptr, s.waves(), s.fp32, s.rot(), h->st));
-    s.step += nsteps;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        HIPCHK(launch_step(s.dd, nullptr, s.waves(), nullptr, s.step, s.fp32, s.rot(), h->st));
+        if (++s.step - s.red_to >= PART_RING) {
+            int rc = s.reduce_records(h->st);
+            if (rc) return rc;
+        }
+    }
     return PDBM_OK;
 }
 
@@ -439,6 +453,8 @@ int pdbm_diag_history(pdbm_solver *h, pdbm_diag *out, int32_t cap, int32_t *n)
 {
     if (!h || !n || cap < 0 || (cap > 0 && !out)) return fail(PDBM_EINVAL, "bad argument");
     Solve &s = h->s;
+    int rc = s.reduce_records(h->st);
+    if (rc) return rc;
     HIPCHK(hipStreamSynchronize(h->st));
     *n = 0;
     const int64_t de = s.p.diag_every;

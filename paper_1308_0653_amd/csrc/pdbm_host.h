@@ -45,8 +45,9 @@ class Solve {
     SolveDesc *dd = nullptr;  // device copy read by the step kernel
     double *cpart = nullptr;  // moments-kernel reduction scratch
     unsigned *counter = nullptr;
-    int64_t step = 0;      // steps taken (mirrors hd.state->step)
+    int64_t step = 0;      // steps taken (never beyond hd.nsteps)
     int64_t rec_from = 0;  // drift records are valid from this step on
+    int64_t red_to = 0;    // records of steps before this one have been added up
     std::vector<double2> cs_host;  // staging of uploads (kept until the next sync)
     SolveState zero_state{};
 
@@ -62,6 +63,9 @@ class Solve {
     bool rot() const { return p.sector != 8; }
     // Sets the step count on host and device (stream must be idle).
     int set_step(int64_t s, hipStream_t st);
+    // Enqueues the adding up of the drift partial sums of steps [red_to,
+    // step), at most PART_RING steps (single-solve launches only).
+    int reduce_records(hipStream_t st);
     // Fields [6][nr][ntheta] of the current state into device memory `out`
     // and the drift report into `diag_dev` (both enqueued on st).
     int moments(double *out, pdbm_diag *diag_dev, hipStream_t st) const;

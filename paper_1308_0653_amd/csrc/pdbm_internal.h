@@ -12,15 +12,13 @@ namespace pdbm {
 constexpr int NQ = 33;          // D2V33: rest particle + 4 speeds x 8 directions
 constexpr int BLOCK = 256;      // threads per workgroup of the cell kernels
 constexpr int HIST_CAP = 4096;  // drift reports kept per solve
+constexpr int PART_RING = PDBM_MAX_CHUNK;  // records whose partial sums may wait to be added up
 constexpr int NXCD = 8;         // accelerator complex dies of an MI355X
 constexpr int STRIP = 62;       // theta columns stored per wavefront (64 lanes minus 2 halo lanes)
 
-// Mutable per-solve state in device memory, advanced by the step kernel
-// itself so that a captured graph of steps needs no host involvement.
+// Per-solve state in device memory written by the host.
 struct SolveState {
-    int64_t step;         // steps taken; the current f and lambda are buffer (step & 1)
-    uint32_t waves_done;  // wavefronts of the running step that have finished
-    uint32_t pad_;
+    int64_t rec_from;  // drift records are produced for steps >= rec_from only
 };
 
 // Everything a kernel needs to know about one solve.  The step kernel reads
@@ -31,7 +29,7 @@ struct SolveDesc {
     double *lam[2];     // [nr][pitch]
     const double2 *cs;  // [ntheta] (cos theta_j, sin theta_j)
     SolveState *state;
-    double *wpart;      // [nwaves][5] per-wavefront drift partial sums of the running step
+    double *wpart;      // [PART_RING][nwaves][5] per-wavefront drift partial sums, slot (record % PART_RING)
     pdbm_diag *hist;    // [HIST_CAP] drift reports, record k for step k * diag_every
     int32_t nr, nt, pitch, sector;
     int32_t m, n, disc, reacts;          // disc: r_min == 0; reacts: w1+w2 > 0
@@ -64,7 +62,18 @@ struct DiagCtl {
 // tile of that solve), or is NULL for a single solve (descs[0], tiles
 // 0..ntiles-1).  All solves share the precision; `rot` selects the variant
 // for sectors other than the full annulus.
-hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, bool fp32, bool rot, hipStream_t st);
+// The step a solve takes is bases[solve] + step_off (bases NULL: step_off);
+// a solve whose step is at or beyond its nsteps is left alone.  A step that
+// makes a drift record leaves partial sums that launch_records adds up.
+hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
+                       bool fp32, bool rot, hipStream_t st);
+// bases[i] += by for i < n.
+hipError_t launch_advance(int64_t *bases, int n, int64_t by, hipStream_t st);
+// Drift records of steps [base + lo, base + hi) of solves descs[0..n), base =
+// bases[i] (0 if bases is NULL); at most PART_RING steps per call, and the
+// steps must have been launched before on the same stream.
+hipError_t launch_records(const SolveDesc *descs, int n, const int64_t *bases, int64_t lo, int64_t hi,
+                          hipStream_t st);
 // Cell kernels on buffer `cur` of one solve.
 hipError_t launch_init_ic(const SolveDesc &d, int cur, bool fp32, const pdbm_ic &ic, hipStream_t st);
 hipError_t launch_init_fields(const SolveDesc &d, int cur, bool fp32, const double *fields, hipStream_t st);

@@ -534,59 +534,22 @@ struct StepOcc {
     static constexpr int waves = sizeof(real) == 4 ? 2 : 1;
 };
 
-// End of a wavefront's share of one step of one solve.  On a drift-report
-// step the wavefront's partial sums go to the solve's slot for it; the last
-// wavefront of the solve to finish adds all slots in a fixed order (the
-// report is the same whatever the finishing order), writes the record, and
-// advances the solve's step counter for the next launch.
-__device__ __forceinline__ void finish_wave(DescPtr dp, int lt, int64_t step, double red[5], bool diag)
+// Whether step `s` of a solve makes a drift record.
+__device__ __forceinline__ bool records(DescPtr dp, int64_t s)
 {
-    const int lane = threadIdx.x & 63;
-    if (diag) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            const double v = wave_sum(red[i]);
-            if (lane == 0) dp->wpart[5 * (size_t)lt + i] = v;
-        }
-    }
-    __threadfence();
-    unsigned done = 0;
-    if (lane == 0) done = atomicAdd(&dp->state->waves_done, 1u);
-    done = __builtin_amdgcn_readfirstlane(done);
-    if (done != (unsigned)(dp->nwaves - 1)) return;
-    __threadfence();
-    if (diag) {
-        double acc[5] = {0, 0, 0, 0, 0};
-        for (int w = lane; w < dp->nwaves; w += 64)
-#pragma unroll
-            for (int i = 0; i < 5; ++i)
-                acc[i] += __hip_atomic_load(dp->wpart + 5 * (size_t)w + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-        for (int i = 0; i < 5; ++i) acc[i] = wave_sum(acc[i]);
-        if (lane == 0) {
-            pdbm_diag r;
-            r.step = step;
-            r.mass = acc[0];
-            r.energy = acc[1];
-            r.chem = acc[2];
-            r.n_nonfinite = (int64_t)acc[3];
-            r.n_nonphys = (int64_t)acc[4];
-            dp->hist[(step / dp->diag_every) % HIST_CAP] = r;
-        }
-    }
-    if (lane == 0) {
-        __hip_atomic_store(&dp->state->waves_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&dp->state->step, step + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    return dp->diag_every > 0 && s >= dp->state->rec_from && s % dp->diag_every == 0;
 }
 
 // One time step of every solve of the launch.  Wavefront w of the grid takes
 // tile t = (its block's XCD-ordered index) * 4 + w, which the tile table maps
 // to (solve, tile of that solve); a solve's tile lt is row block lt / nstrip,
-// strip lt % nstrip.  Each wavefront works on its own: no block barriers.
+// strip lt % nstrip.  Each wavefront works on its own: no barriers and no
+// atomics.  A drift-report step leaves per-wavefront partial sums in its
+// slot of the solve's partial-sum ring; k_records adds them up later.
 template <typename real, bool ROT>
 __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const SolveDesc *descs, const uint2 *tiles,
-                                                                       int ntiles)
+                                                                       int ntiles, const int64_t *bases,
+                                                                       int64_t step_off)
 {
     const int nb = gridDim.x;
     const int blk = xcd_tile(blockIdx.x, nb);
@@ -601,9 +564,9 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
         lt = __builtin_amdgcn_readfirstlane((int)e.y);
     }
     const DescPtr dp = (DescPtr)(descs + solve);
-    const int64_t step = dp->state->step;  // advanced only after all of this solve's wavefronts are done
+    const int64_t step = (bases ? bases[solve] : 0) + step_off;
     if (step >= dp->nsteps) return;
-    const bool diag = dp->diag_every > 0 && step % dp->diag_every == 0;
+    const bool diag = records(dp, step);
     const int cur = (int)(step & 1);
     const StepBufs bufs{dp->f[cur], dp->f[cur ^ 1], dp->lam[cur], dp->lam[cur ^ 1]};
     __shared__ real prev[BLOCK / 64][NQ][64];
@@ -616,7 +579,55 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
     const int i0 = rb * rows;
     const int i1 = min(i0 + rows, dp->nr);
     march<real, ROT>(dp, bufs, strip, i0, i1, (rb & 1) != 0, prev[threadIdx.x >> 6], red, diag);
-    finish_wave(dp, lt, step, red, diag);
+    if (diag) {
+        const int64_t slot = (step / dp->diag_every) % PART_RING;
+        double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double v = wave_sum(red[i]);
+            if ((threadIdx.x & 63) == 0) part[i] = v;
+        }
+    }
+}
+
+__global__ void k_advance(int64_t *bases, int n, int64_t by)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) bases[i] += by;
+}
+
+// Drift records of the steps [base + lo, base + hi) of each solve, where base
+// is bases[solve] (0 without bases): block (solve, r) adds up the partial sums
+// of the r-th record in that range, one wavefront, in a fixed order, so the
+// record does not depend on the order in which wavefronts finished.
+__global__ __launch_bounds__(64) void k_records(const SolveDesc *descs, const int64_t *bases, int64_t lo, int64_t hi)
+{
+    const DescPtr dp = (DescPtr)(descs + blockIdx.x);
+    const int64_t de = dp->diag_every;
+    if (de <= 0) return;
+    const int64_t base = bases ? bases[blockIdx.x] : 0;
+    const int64_t s0 = max(base + lo, dp->state->rec_from);
+    const int64_t s1 = min(base + hi, dp->nsteps);
+    const int64_t k = (s0 + de - 1) / de + blockIdx.y;  // record k is step k * de
+    if (s0 >= s1 || k * de >= s1) return;
+    const int lane = threadIdx.x;
+    const double *part = dp->wpart + (size_t)(k % PART_RING) * dp->nwaves * 5;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int w = lane; w < dp->nwaves; w += 64)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i] += part[5 * (size_t)w + i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) acc[i] = wave_sum(acc[i]);
+    if (lane == 0) {
+        pdbm_diag r;
+        r.step = k * de;
+        r.mass = acc[0];
+        r.energy = acc[1];
+        r.chem = acc[2];
+        r.n_nonfinite = (int64_t)acc[3];
+        r.n_nonphys = (int64_t)acc[4];
+        dp->hist[k % HIST_CAP] = r;
+    }
 }
 
 // -------------------------------------------------------------- moments --
@@ -729,21 +740,41 @@ int solve_waves(int nr, int nt, int rows)
     return (int)((int64_t)((nr + rows - 1) / rows) * ((nt + STRIP - 1) / STRIP));
 }
 
-hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, bool fp32, bool rot, hipStream_t st)
+hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
+                       bool fp32, bool rot, hipStream_t st)
 {
     const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0) return hipSuccess;
     if (fp32) {
         if (rot)
-            hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles);
+            hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off);
         else
-            hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles);
+            hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off);
     } else {
         if (rot)
-            hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles);
+            hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off);
         else
-            hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles);
+            hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(int64_t *bases, int n, int64_t by, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, st, bases, n, by);
+    return hipGetLastError();
+}
+
+hipError_t launch_records(const SolveDesc *descs, int n, const int64_t *bases, int64_t lo, int64_t hi, hipStream_t st)
+{
+    if (n <= 0 || hi <= lo) return hipSuccess;
+    const int nrec = (int)std::min<int64_t>(hi - lo, PART_RING);
+    hipLaunchKernelGGL(k_records, dim3(n, nrec), dim3(64), 0, st, descs, bases, lo, hi);
     return hipGetLastError();
 }
 

@@ -4,8 +4,9 @@
 // Every member keeps its own state resident in HBM.  One launch of the step
 // kernel advances all members by one step: its wavefront tiles are the
 // concatenation of the members' tiles, mapped back to (member, tile) by a
-// device table, and each member's step counter, buffer parity and drift
-// report live in its own device memory.  A chunk of such launches is
+// device table.  Member i takes step bases[i] + (the launch's place in the
+// chunk); a small kernel at the end of a chunk adds up the chunk's drift
+// records and advances bases[] by the chunk, so a chunk of launches is
 // captured once in a hipGraph and replayed; membership changes only between
 // chunks.  Members never read each other's data, so a solve's fields are the
 // same bit for bit alone or in any mix.
@@ -41,25 +42,30 @@ class Pack {
 
     ~Pack() { destroy(); }
 
-    // Uploads the description and tile tables of the current members and
-    // drops the captured graph.  Synchronises st.
+    // Uploads the description, step-base and tile tables of the current
+    // members and drops the captured graph.  Synchronises st.
     int rebuild(hipStream_t st)
     {
         drop_graph();
         rot = false;
         std::vector<SolveDesc> descs;
         std::vector<uint2> tiles;
+        bases_host.clear();
         for (size_t i = 0; i < members.size(); ++i) {
             descs.push_back(members[i]->hd);
+            bases_host.push_back(members[i]->step);
             rot = rot || members[i]->rot();
             for (int t = 0; t < members[i]->waves(); ++t) tiles.push_back(make_uint2((unsigned)i, (unsigned)t));
         }
         ntiles = (int)tiles.size();
         int rc = grow((void **)&ddescs, cap_descs, descs.size() * sizeof(SolveDesc));
         if (rc == PDBM_OK) rc = grow((void **)&dtiles, cap_tiles, tiles.size() * sizeof(uint2));
+        if (rc == PDBM_OK) rc = grow((void **)&dbases, cap_bases, bases_host.size() * sizeof(int64_t));
         if (rc) return rc;
         if (!descs.empty()) {
             HIPCHK(hipMemcpyAsync(ddescs, descs.data(), descs.size() * sizeof(SolveDesc), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(dbases, bases_host.data(), bases_host.size() * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(uint2), hipMemcpyHostToDevice, st));
         }
         HIPCHK(hipStreamSynchronize(st));
@@ -67,11 +73,13 @@ class Pack {
         return PDBM_OK;
     }
 
-    // Enqueues `steps` steps of every member: whole chunks by replaying the
-    // captured graph, the rest as plain launches.
+    // Enqueues `steps` steps of every member (a member stops at its own
+    // step limit): whole chunks by replaying the captured graph, the rest as
+    // plain launches.  chunk <= PART_RING.
     int run(int64_t steps, int chunk, hipStream_t st)
     {
         if (members.empty() || steps <= 0) return PDBM_OK;
+        const int64_t total = steps;
         if (chunk > 1 && steps >= chunk) {
             if (!exec || graph_steps != chunk) {
                 int rc = capture(chunk, st);
@@ -79,7 +87,12 @@ class Pack {
             }
             for (; steps >= chunk; steps -= chunk) HIPCHK(hipGraphLaunch(exec, st));
         }
-        for (; steps > 0; --steps) HIPCHK(launch_step(ddescs, dtiles, ntiles, fp32, rot, st));
+        while (steps > 0) {
+            const int n = (int)std::min<int64_t>(steps, PART_RING);
+            HIPCHK(enqueue_steps(n, st));
+            steps -= n;
+        }
+        for (Solve *m : members) m->step = std::min(m->step + total, m->hd.nsteps);
         return PDBM_OK;
     }
 
@@ -88,9 +101,11 @@ class Pack {
         drop_graph();
         if (ddescs) (void)hipFree(ddescs);
         if (dtiles) (void)hipFree(dtiles);
+        if (dbases) (void)hipFree(dbases);
         ddescs = nullptr;
         dtiles = nullptr;
-        cap_descs = cap_tiles = 0;
+        dbases = nullptr;
+        cap_descs = cap_tiles = cap_bases = 0;
     }
 
     int tiles() const { return ntiles; }
@@ -99,7 +114,9 @@ class Pack {
     bool rot = false;
     SolveDesc *ddescs = nullptr;
     uint2 *dtiles = nullptr;
-    size_t cap_descs = 0, cap_tiles = 0;
+    int64_t *dbases = nullptr;  // step of each member at the start of the next chunk
+    std::vector<int64_t> bases_host;
+    size_t cap_descs = 0, cap_tiles = 0, cap_bases = 0;
     int ntiles = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -121,8 +138,7 @@ class Pack {
     {
         drop_graph();
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipSuccess;
-        for (int i = 0; i < chunk && e == hipSuccess; ++i) e = launch_step(ddescs, dtiles, ntiles, fp32, rot, st);
+        const hipError_t e = enqueue_steps(chunk, st);
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(st, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -134,6 +150,18 @@ class Pack {
         HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         graph_steps = chunk;
         return PDBM_OK;
+    }
+
+    // n <= PART_RING steps of every member, their drift records, and the
+    // advance of the step bases.
+    hipError_t enqueue_steps(int n, hipStream_t st)
+    {
+        const int nm = (int)members.size();
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_step(ddescs, dtiles, ntiles, dbases, i, fp32, rot, st);
+        if (e == hipSuccess) e = launch_records(ddescs, nm, dbases, 0, n, st);
+        if (e == hipSuccess) e = launch_advance(dbases, nm, n, st);
+        return e;
     }
 
     void drop_graph()
@@ -189,7 +217,7 @@ extern "C" {
 int pdbm_batch_create(int32_t n, const pdbm_params *ps, const pdbm_ic *ics, int32_t chunk_steps, void *stream,
                       pdbm_batch **out)
 {
-    if (!out || n < 1 || !ps || chunk_steps < 0) return fail(PDBM_EINVAL, "bad argument");
+    if (!out || n < 1 || !ps || chunk_steps < 0 || chunk_steps > PART_RING) return fail(PDBM_EINVAL, "bad argument");
     *out = nullptr;
     for (int i = 0; i < n; ++i) {
         int rc = pdbm_validate(ps + i, ics ? ics + i : nullptr, nullptr);
@@ -238,10 +266,7 @@ void pdbm_batch_destroy(pdbm_batch *b)
 int pdbm_batch_step(pdbm_batch *b, int64_t nsteps)
 {
     if (!b || nsteps < 0) return fail(PDBM_EINVAL, "bad batch or step count");
-    int rc = b->pack.run(nsteps, b->chunk, b->st);
-    if (rc) return rc;
-    for (auto &s : b->solves) s->step += nsteps;
-    return PDBM_OK;
+    return b->pack.run(nsteps, b->chunk, b->st);
 }
 
 int64_t pdbm_batch_step_count(const pdbm_batch *b, int32_t i)
@@ -427,10 +452,6 @@ int pdbm_server::admit_and_step(std::vector<Request *> &admitted)
         int rc = pack[k].run(chunk, chunk, st);
         if (rc) return rc;
     }
-    std::vector<int64_t> steps(running.size());
-    for (size_t i = 0; i < running.size(); ++i)
-        HIPCHK(hipMemcpyAsync(&steps[i], &running[i]->solve->hd.state->step, sizeof(int64_t), hipMemcpyDeviceToHost,
-                              st));
     HIPCHK(hipStreamSynchronize(st));
     {
         std::lock_guard<std::mutex> g(mu);
@@ -439,8 +460,7 @@ int pdbm_server::admit_and_step(std::vector<Request *> &admitted)
     std::vector<Request *> still;
     for (size_t i = 0; i < running.size(); ++i) {
         Request *r = running[i];
-        r->solve->step = steps[i];
-        if (steps[i] >= r->nsteps) {
+        if (r->solve->step >= r->nsteps) {
             auto &m = pack[r->p.precision].members;
             m.erase(std::find(m.begin(), m.end(), r->solve.get()));
             pack[r->p.precision].dirty = true;
@@ -458,7 +478,8 @@ extern "C" {
 int pdbm_server_create(size_t hbm_cap_bytes, int32_t max_slots, int32_t chunk_steps, void *stream,
                        pdbm_server **out)
 {
-    if (!out || hbm_cap_bytes == 0 || max_slots < 1 || chunk_steps < 1) return fail(PDBM_EINVAL, "bad argument");
+    if (!out || hbm_cap_bytes == 0 || max_slots < 1 || chunk_steps < 1 || chunk_steps > PART_RING)
+        return fail(PDBM_EINVAL, "bad argument");
     *out = nullptr;
     int rc = check_device();
     if (rc) return rc;
