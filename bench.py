@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--batch-solves", type=int, default=256, help="solves of the packed parameter sweep")
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of each solve of the sweep")
     ap.add_argument("--serving-requests", type=int, default=120,
-                    help="requests of the Poisson serving stream (1000 in the full workload)")
+                    help="requests of the Poisson serving stream (1000 in the full workload; 0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -264,9 +264,10 @@ def main():
     if not a.no_serving:
         sweep = packed_sweep(P, W, torch, a.batch_solves, a.batch_steps)
         out["packed_sweep"] = sweep
-        served, serial = serving_stream(P, W, torch, a.serving_requests, sweep["value"])
-        out["serving"] = {"served_fp32": served, "serial_fp64": serial,
-                          "workload": f"poisson{a.serving_requests}_logU"}
+        if a.serving_requests > 0:
+            served, serial = serving_stream(P, W, torch, a.serving_requests, sweep["value"])
+            out["serving"] = {"served_fp32": served, "serial_fp64": serial,
+                              "workload": f"poisson{a.serving_requests}_logU"}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out))
