@@ -74,6 +74,8 @@ def lib(real: str = "double"):
         L.ora_collide.argtypes = [C.POINTER(Params), dp, C.c_double, C.c_double, dp, dp]
         L.ora_cochran.argtypes = [C.c_double] * 4
         L.ora_cochran.restype = C.c_double
+        L.ora_noneq.argtypes = [vp, dp]
+        L.ora_central_moments.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp]
         L.ora_splitmix64.argtypes = [C.c_uint64]
         L.ora_splitmix64.restype = C.c_uint64
         L.ora_real_bytes.restype = C.c_int
@@ -123,6 +125,18 @@ def collide(params: Params, f, lam, theta):
 
 def cochran(lam, a, b, dt) -> float:
     return lib().ora_cochran(float(lam), float(a), float(b), float(dt))
+
+
+NONEQ_NAMES = ("D2_rr", "D2_rt", "D2_tt", "D3_rrr", "D3_rrt", "D3_rtt", "D3_ttt",
+               "D31_r", "D31_t", "D42_rr", "D42_rt", "D42_tt")
+
+
+def central_moments(g, theta, ur, ut) -> np.ndarray:
+    """M*_2, M*_3, M*_{3,1}, M*_{4,2} of g about (u_r, u_theta), in the order of
+    NONEQ_NAMES (Sec. II.E)."""
+    out = np.zeros(12)
+    lib().ora_central_moments(np.ascontiguousarray(g, dtype=np.float64), float(theta), float(ur), float(ut), out)
+    return out
 
 
 def splitmix64(x: int) -> int:
@@ -185,6 +199,14 @@ class Solver:
         nr, nt = self.shape
         out = np.zeros((6, nr, nt))
         self.L.ora_fields(self.h, out)
+        return out
+
+    def noneq(self) -> np.ndarray:
+        """[12][nr][ntheta] non-equilibrium measures Delta*_m (Sec. II.E), in
+        the order of NONEQ_NAMES."""
+        nr, nt = self.shape
+        out = np.zeros((12, nr, nt))
+        self.L.ora_noneq(self.h, out)
         return out
 
     def diag(self):

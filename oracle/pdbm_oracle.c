@@ -429,6 +429,53 @@ void ora_fields(ora_state *s, double *out)
         }
 }
 
+/* Central moments of a distribution g about the velocity u (Sec. II.E),
+ * in the polar components of the cell's frame, v* = v - u:
+ *   M*_2     = sum g v* v*               -> out[0..2]  = rr, r theta, theta theta
+ *   M*_3     = sum g v* v* v*            -> out[3..6]  = rrr, rr theta, r theta theta, theta theta theta
+ *   M*_{3,1} = sum 1/2 g (v*.v*) v*      -> out[7..8]  = r, theta
+ *   M*_{4,2} = sum 1/2 g (v*.v*) v* v*   -> out[9..11] = rr, r theta, theta theta */
+static void central_moments(const real g[NQ], const real vr[NQ], const real vt[NQ], real ur, real ut, real out[12])
+{
+    for (int m = 0; m < 12; ++m) out[m] = 0;
+    for (int q = 0; q < NQ; ++q) {
+        real cr = vr[q] - ur, ct = vt[q] - ut;
+        real h = (real)0.5 * (cr * cr + ct * ct);
+        out[0] += g[q] * cr * cr;
+        out[1] += g[q] * cr * ct;
+        out[2] += g[q] * ct * ct;
+        out[3] += g[q] * cr * cr * cr;
+        out[4] += g[q] * cr * cr * ct;
+        out[5] += g[q] * cr * ct * ct;
+        out[6] += g[q] * ct * ct * ct;
+        out[7] += g[q] * h * cr;
+        out[8] += g[q] * h * ct;
+        out[9] += g[q] * h * cr * cr;
+        out[10] += g[q] * h * cr * ct;
+        out[11] += g[q] * h * ct * ct;
+    }
+}
+
+/* Non-equilibrium manifestations Delta*_m = M*_m(f) - M*_m(f^eq) of every
+ * cell (Sec. II.E), u and f^eq from the cell's own moments; out is
+ * [12][nr][ntheta] in the component order of central_moments. */
+void ora_noneq(ora_state *s, double *out)
+{
+    int nr = s->p.nr, nt = s->p.ntheta;
+    size_t nc = (size_t)nr * nt;
+    for (int ir = 0; ir < nr; ++ir)
+        for (int jt = 0; jt < nt; ++jt) {
+            const real *vr = s->vr + jt * NQ, *vt = s->vt + jt * NQ;
+            const real *f = F_AT(s, s->f, ir, jt);
+            real rho, ur, ut, T, feq[NQ], mf[12], me[12];
+            moments(f, vr, vt, &rho, &ur, &ut, &T);
+            equilibrium(rho, ur, ut, T, vr, vt, feq);
+            central_moments(f, vr, vt, ur, ut, mf);
+            central_moments(feq, vr, vt, ur, ut, me);
+            for (int m = 0; m < 12; ++m) out[m * nc + (size_t)ir * nt + jt] = (double)(mf[m] - me[m]);
+        }
+}
+
 /* Global drift report: area-weighted sums over cells (weight r_i dr dtheta)
  * of mass rho, total energy rho T + rho u^2 / 2 and unreleased chemical
  * energy rho Q (1 - lambda); counts of cells with a non-finite value and of
@@ -518,6 +565,16 @@ void ora_collide(const ora_params *p, const double f[NQ], double lam, double the
 }
 
 double ora_cochran(double lam, double a, double b, double dt) { return (double)cochran(lam, a, b, dt); }
+
+/* Central moments (Sec. II.E) of g[33] about (u_r, u_theta) at azimuth theta. */
+void ora_central_moments(const double g[NQ], double theta, double ur, double ut, double out[12])
+{
+    real vr[NQ], vt[NQ], gr[NQ], o[12];
+    velocities((real)theta, vr, vt);
+    for (int q = 0; q < NQ; ++q) gr[q] = (real)g[q];
+    central_moments(gr, vr, vt, (real)ur, (real)ut, o);
+    for (int m = 0; m < 12; ++m) out[m] = (double)o[m];
+}
 
 uint64_t ora_splitmix64(uint64_t x) { return splitmix64(x); }
 

@@ -667,3 +667,136 @@ def test_disc_centre_rule_is_consistent_transport():
     for nr in (20, 40):
         e = _disc_ring_errors(nr)
         assert e[0] <= 1.2 * e[1], (nr, e[:3])
+
+
+# ------------------------------------------------- non-equilibrium (II.E) --
+# component order of the Delta*_m output: M*_2 rr, rt, tt; M*_3 rrr, rrt,
+# rtt, ttt; M*_{3,1} r, t; M*_{4,2} rr, rt, tt
+_THETA_PARITY = np.array([1, -1, 1, 1, -1, 1, -1, 1, -1, 1, -1, 1])
+
+
+def _two_beam_expected(rho, T, dr, dt_):
+    """Delta*_m of f = (f^eq(rho, u + d, T) + f^eq(rho, u - d, T)) / 2, a
+    mixture of two equilibria drifting at +-d relative to the mean u.  From
+    the Maxwellian moments (which f^eq reproduces up to M*_{4,2}, Sec. II.B):
+    central M*_2 = rho T I + rho d d and the mixture temperature is
+    T + |d|^2/2, so Delta*_2 = rho (d d - |d|^2/2 I); odd moments cancel
+    between the beams; and
+    Delta*_{4,2} = rho (3T d d - 3/2 T |d|^2 I + 1/2 |d|^2 d d - 1/2 |d|^4 I)."""
+    d = np.array([dr, dt_])
+    d2 = d @ d
+    I = np.eye(2)
+    D2 = rho * (np.outer(d, d) - 0.5 * d2 * I)
+    D42 = rho * (3 * T * np.outer(d, d) - 1.5 * T * d2 * I + 0.5 * d2 * np.outer(d, d) - 0.5 * d2 * d2 * I)
+    return np.array([D2[0, 0], D2[0, 1], D2[1, 1], 0, 0, 0, 0, 0, 0, D42[0, 0], D42[0, 1], D42[1, 1]])
+
+
+@pytest.mark.parametrize("rho,T,ur,ut,dr,dt_", [(1.3, 2.0, 0.2, -0.1, 0.3, 0.15), (0.7, 5.0, -0.5, 0.4, -0.2, 0.6),
+                                                 (2.0, 1.2, 0.0, 0.0, 0.05, -0.02)])
+def test_noneq_two_beam_mixture_closed_form(rho, T, ur, ut, dr, dt_):
+    """Sec. II.E on a state whose non-equilibrium is known in closed form:
+    two interpenetrating equilibria (a mixture of beams at u +- d)."""
+    p = O.make_params(1, 1, 0.5, 1.0, dt=1e-5, tau=2e-5)
+    theta = math.pi  # the single cell of a full annulus with N_theta = 1
+    f = 0.5 * (O.equilibrium(rho, ur + dr, ut + dt_, T, theta) + O.equilibrium(rho, ur - dr, ut - dt_, T, theta))
+    s = O.Solver(p)
+    s.set_state(f.reshape(1, 1, 33), np.zeros((1, 1)))
+    got = s.noneq()[:, 0, 0]
+    ref = _two_beam_expected(rho, T, dr, dt_)
+    scale = rho * (T + dr * dr + dt_ * dt_) ** 2
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)
+    # the mixture does depart from equilibrium
+    assert np.abs(got).max() > 0.1 * rho * (dr * dr + dt_ * dt_)
+
+
+def test_noneq_relations_of_the_paper():
+    """Sec. II.E: Delta*_{3,1,r} = (Delta*_{3,rrr} + Delta*_{3,r theta theta})/2,
+    Delta*_{3,1,theta} = (Delta*_{3,rr theta} + Delta*_{3,theta theta theta})/2,
+    and Delta*_{2,rr} = -Delta*_{2,theta theta} (f^eq carries the cell's own
+    energy), for an arbitrary non-equilibrium state."""
+    rng = np.random.default_rng(11)
+    nr, nt = 6, 16
+    p = O.make_params(nr, nt, 0.2, 1.0, dt=1e-5, tau=2e-5)
+    f = np.empty((nr, nt, 33))
+    for ir in range(nr):
+        for jt in range(nt):
+            th = (jt + 0.5) * 2 * math.pi / nt
+            feq = O.equilibrium(rng.uniform(0.5, 2), rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5),
+                                rng.uniform(0.8, 6), th)
+            f[ir, jt] = feq * (1 + 0.05 * rng.uniform(-1, 1, 33))
+    s = O.Solver(p)
+    s.set_state(f, np.zeros((nr, nt)))
+    D = s.noneq()
+    F = s.fields()
+    s3 = (F[0] * F[3] ** 1.5).max()
+    assert np.abs(D[7] - 0.5 * (D[3] + D[5])).max() < 1e-12 * s3
+    assert np.abs(D[8] - 0.5 * (D[4] + D[6])).max() < 1e-12 * s3
+    assert np.abs(D[0] + D[2]).max() < 1e-12 * (F[0] * F[3]).max()
+    assert np.abs(D[0]).max() > 1e-4 * (F[0] * F[3]).max()
+
+
+def test_noneq_central_moments_match_cartesian_tensors():
+    """The polar central moments equal the Cartesian tensors of the same
+    distribution, built here from the speeds and the directions i pi/4 alone,
+    rotated into the frame (e_r, e_theta) at theta."""
+    rng = np.random.default_rng(12)
+    g = rng.uniform(-1, 1, 33)
+    theta, ux, uy = 0.7, 0.3, -0.2
+    vx, vy = np.zeros(33), np.zeros(33)
+    for q in range(1, 33):
+        v, a = SPEEDS[_k_of(q)], _i_of(q) * math.pi / 4
+        vx[q], vy[q] = v * math.cos(a), v * math.sin(a)
+    cx, cy = vx - ux, vy - uy
+    c = np.stack([cx, cy])
+    h = 0.5 * (cx * cx + cy * cy)
+    M2 = np.einsum("q,aq,bq->ab", g, c, c)
+    M3 = np.einsum("q,aq,bq,cq->abc", g, c, c, c)
+    M31 = np.einsum("q,q,aq->a", g, h, c)
+    M42 = np.einsum("q,q,aq,bq->ab", g, h, c, c)
+    R = np.array([[math.cos(theta), math.sin(theta)], [-math.sin(theta), math.cos(theta)]])  # rows e_r, e_theta
+    M2p = R @ M2 @ R.T
+    M3p = np.einsum("ia,jb,kc,abc->ijk", R, R, R, M3)
+    M31p = R @ M31
+    M42p = R @ M42 @ R.T
+    ref = np.array([M2p[0, 0], M2p[0, 1], M2p[1, 1], M3p[0, 0, 0], M3p[0, 0, 1], M3p[0, 1, 1], M3p[1, 1, 1],
+                    M31p[0], M31p[1], M42p[0, 0], M42p[0, 1], M42p[1, 1]])
+    ur, ut = R @ np.array([ux, uy])
+    got = O.central_moments(g, theta, ur, ut)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_noneq_rotation_and_mirror_symmetry():
+    """An axisymmetric run is invariant under rotation by pi/4 and under the
+    mirror theta -> -theta (P8).  Polar components are frame-relative: they
+    repeat under the rotation, and those with an odd number of theta indices
+    change sign under the mirror."""
+    nr, nt = 12, 24
+    p = O.make_params(nr, nt, 0.1, 1.0, dt=1e-4, tau=2e-4, w1=2, w2=2, m=2, n=2, Q=1.0, T_th=1.1)
+    s = O.Solver(p)
+    s.init_ic(0.35, [1.5, 20 / 1.5, 0, 0, 1], [1, 1, 0, 0, 0])
+    s.step(40)
+    D = s.noneq()
+    scale = np.abs(D).max()
+    assert np.abs(np.roll(D, nt // 8, axis=2) - D).max() < 1e-11 * scale
+    assert np.abs(_THETA_PARITY[:, None, None] * D[:, :, ::-1] - D).max() < 1e-11 * scale
+    assert np.abs(D[0]).max() > 1e-3 * scale  # the detonation front is out of equilibrium
+
+
+def test_noneq_decays_with_pure_relaxation():
+    """With no reaction and no gradients (P5), f - f^eq decays as
+    exp(-t/tau) at fixed moments, so every Delta*_m does too."""
+    rng = np.random.default_rng(13)
+    nr, nt = 4, 8
+    p = O.make_params(nr, nt, 0.5, 1.0, dt=1e-5, tau=3e-5, w1=0, w2=0, m=1, n=1, Q=0.0, T_th=1.1)
+    feq = O.equilibrium(1.1, 0.0, 0.0, 1.7, 0.0)
+    vr, vt = O.velocities(0.0)
+    Bm = np.stack([np.ones(33), vr, vt, 0.5 * (vr * vr + vt * vt)])
+    d = 0.03 * feq * rng.uniform(-1, 1, 33)
+    d -= Bm.T @ np.linalg.lstsq(Bm.T, d, rcond=None)[0]
+    s = O.Solver(p)
+    s.set_state(np.broadcast_to(feq + d, (nr, nt, 33)).copy(), np.zeros((nr, nt)))
+    D0 = s.noneq()
+    n = 20
+    s.step(n)
+    D1 = s.noneq()
+    np.testing.assert_allclose(D1, D0 * math.exp(-n * p.dt / p.tau), rtol=0, atol=1e-11 * np.abs(D0).max())
