@@ -182,6 +182,27 @@ int pdbm_moments(pdbm_solver *s, double *out, pdbm_diag *diag);
  * memory [6][nr][ntheta] float64 without synchronising. */
 int pdbm_moments_async(pdbm_solver *s, void *out_device);
 
+/* Non-equilibrium measures of Sec. II.E ("non-equilibrium characteristics"):
+ * Delta*_m = M*_m(f) - M*_m(f^eq), the central moments about the cell's own
+ * u of f minus those of its equilibrium, in polar components of the cell's
+ * frame (e_r, e_theta at theta_j):
+ *   M*_2     = sum f v* v*              M*_3     = sum f v* v* v*
+ *   M*_{3,1} = sum 1/2 f (v*.v*) v*     M*_{4,2} = sum 1/2 f (v*.v*) v* v*
+ * with v* = v - u, computed in float64 (also for an FP32 solver).  `out`:
+ * host [PDBM_NONEQ_N][nr][ntheta] float64, components in the order of the
+ * enum below.  Synchronises the stream. */
+enum {
+    PDBM_NONEQ_D2_RR, PDBM_NONEQ_D2_RT, PDBM_NONEQ_D2_TT,
+    PDBM_NONEQ_D3_RRR, PDBM_NONEQ_D3_RRT, PDBM_NONEQ_D3_RTT, PDBM_NONEQ_D3_TTT,
+    PDBM_NONEQ_D31_R, PDBM_NONEQ_D31_T,
+    PDBM_NONEQ_D42_RR, PDBM_NONEQ_D42_RT, PDBM_NONEQ_D42_TT,
+    PDBM_NONEQ_N
+};
+int pdbm_noneq(pdbm_solver *s, double *out);
+/* As pdbm_noneq, enqueued on the stream into caller-owned device memory
+ * [PDBM_NONEQ_N][nr][ntheta] float64 without synchronising. */
+int pdbm_noneq_async(pdbm_solver *s, void *out_device);
+
 /* Copies up to `cap` of the most recent drift reports recorded while
  * stepping (oldest first) into `out`; *n receives how many.  At most 4096
  * are kept.  Synchronises the stream. */
@@ -221,6 +242,8 @@ int pdbm_batch_step(pdbm_batch *b, int64_t nsteps);
 int64_t pdbm_batch_step_count(const pdbm_batch *b, int32_t i);
 /* As pdbm_moments, for member i. */
 int pdbm_batch_moments(pdbm_batch *b, int32_t i, double *out, pdbm_diag *diag);
+/* As pdbm_noneq, for member i. */
+int pdbm_batch_noneq(pdbm_batch *b, int32_t i, double *out);
 
 /* ------------------------------------------------- continuous batching -- */
 /* A request server: submitted solves wait in a first-come-first-served queue

@@ -348,6 +348,17 @@ int Solve::moments(double *out, pdbm_diag *diag_dev, hipStream_t st) const
     return PDBM_OK;
 }
 
+int pdbm::noneq_to_host(const Solve &s, double *out, hipStream_t st)
+{
+    // the idle f buffer (at least 33 x 4 bytes per cell) stages the 12 float64 values
+    double *stage = (double *)s.hd.f[s.cur() ^ 1];
+    HIPCHK(launch_noneq(s.hd, s.cur(), s.fp32, stage, st));
+    HIPCHK(hipMemcpyAsync(out, stage, (size_t)NONEQ * s.p.nr * s.p.ntheta * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PDBM_OK;
+}
+
 // ------------------------------------------------------------ one solve ABI --
 struct pdbm_solver {
     Solve s;
@@ -447,6 +458,20 @@ int pdbm_moments_async(pdbm_solver *h, void *out_device)
 {
     if (!h || !out_device) return fail(PDBM_EINVAL, "NULL argument");
     return h->s.moments((double *)out_device, h->s.hd.hist + HIST_CAP, h->st);
+}
+
+int pdbm_noneq(pdbm_solver *h, double *out)
+{
+    if (!h || !out) return fail(PDBM_EINVAL, "NULL argument");
+    Solve &s = h->s;
+    return noneq_to_host(s, out, h->st);
+}
+
+int pdbm_noneq_async(pdbm_solver *h, void *out_device)
+{
+    if (!h || !out_device) return fail(PDBM_EINVAL, "NULL argument");
+    HIPCHK(launch_noneq(h->s.hd, h->s.cur(), h->s.fp32, (double *)out_device, h->st));
+    return PDBM_OK;
 }
 
 int pdbm_diag_history(pdbm_solver *h, pdbm_diag *out, int32_t cap, int32_t *n)

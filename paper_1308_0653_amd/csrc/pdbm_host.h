@@ -31,6 +31,10 @@ struct Layout {
 };
 
 Layout layout_of(const pdbm_params &p, int rows);
+class Solve;
+// Non-equilibrium measures of the current state into host `out`
+// [NONEQ][nr][ntheta] (staged in the idle f buffer; synchronises st).
+int noneq_to_host(const Solve &s, double *out, hipStream_t st);
 int check_device();
 
 // One solve resident on the GPU: its buffers, the description its kernels

@@ -14,6 +14,7 @@ constexpr int BLOCK = 256;      // threads per workgroup of the cell kernels
 constexpr int HIST_CAP = 4096;  // drift reports kept per solve
 constexpr int PART_RING = PDBM_MAX_CHUNK;  // records whose partial sums may wait to be added up
 constexpr int NXCD = 8;         // accelerator complex dies of an MI355X
+constexpr int NONEQ = PDBM_NONEQ_N;  // components of the non-equilibrium measures
 constexpr int STRIP = 62;       // theta columns stored per wavefront (64 lanes minus 2 halo lanes)
 
 // Per-solve state in device memory written by the host.
@@ -67,6 +68,9 @@ struct DiagCtl {
 // makes a drift record leaves partial sums that launch_records adds up.
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
                        bool fp32, bool rot, hipStream_t st);
+// Non-equilibrium measures (Sec. II.E) of the state in buffer `cur` into
+// device memory out [NONEQ][nr][nt] float64.
+hipError_t launch_noneq(const SolveDesc &d, int cur, bool fp32, double *out, hipStream_t st);
 // bases[i] += by for i < n.
 hipError_t launch_advance(int64_t *bases, int n, int64_t by, hipStream_t st);
 // Drift records of steps [base + lo, base + hi) of solves descs[0..n), base =

@@ -668,6 +668,69 @@ __global__ __launch_bounds__(BLOCK) void k_moments(SolveDesc d, int cur, double 
     diag_reduce(dc, red, blockIdx.x, nb);
 }
 
+// ----------------------------------------------------- non-equilibrium --
+// Delta*_m = M*_m(f) - M*_m(f^eq) of every cell (Sec. II.E): central moments
+// about the cell's u in its polar frame (e_r, e_theta at theta_j), taken as
+// the moments of f - f^eq.  Float64 throughout.  out: [NONEQ][nr][nt] in the
+// order M*_2 rr, r theta, theta theta; M*_3 rrr, rr theta, r theta theta,
+// theta theta theta; M*_{3,1} r, theta; M*_{4,2} rr, r theta, theta theta.
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_noneq(SolveDesc d, int cur, double *out)
+{
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    const int ncell = d.nr * d.nt;
+    if (c >= ncell) return;
+    const int ir = c / d.nt;
+    const int jt = c - ir * d.nt;
+    const real *fin = (const real *)d.f[cur];
+    const int64_t fidx = (int64_t)ir * d.rstride + jt;
+    double f[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) f[q] = (double)fin[q * d.plane + fidx];
+    double rho, jx, jy, e;
+    raw_moments(f, rho, jx, jy, e);
+    const double ux = jx / rho, uy = jy / rho;
+    const double T = e / rho - 0.5 * (ux * ux + uy * uy);
+    double g[NQ];
+    equilibrium<double>(d.A, rho, ux, uy, T, g);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) g[q] = f[q] - g[q];
+    const double2 cs = d.cs[jt];
+    const double ur = ux * cs.x + uy * cs.y, ut = -ux * cs.y + uy * cs.x;
+    // cos and sin of the directions i pi/4
+    constexpr double DX[8] = {1.0, SQH, 0.0, -SQH, -1.0, -SQH, 0.0, SQH};
+    constexpr double DY[8] = {0.0, SQH, 1.0, SQH, 0.0, -SQH, -1.0, -SQH};
+    double m[NONEQ];
+#pragma unroll
+    for (int k = 0; k < NONEQ; ++k) m[k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double vr = 0.0, vt = 0.0;
+        if (q > 0) {
+            const int k = 1 + (q - 1) / 8, i = (q - 1) % 8;
+            vr = speed(k) * (DX[i] * cs.x + DY[i] * cs.y);  // v cos(i pi/4 - theta)
+            vt = speed(k) * (DY[i] * cs.x - DX[i] * cs.y);  // v sin(i pi/4 - theta)
+        }
+        const double cr = vr - ur, ct = vt - ut;
+        const double h = 0.5 * (cr * cr + ct * ct);
+        const double grr = g[q] * cr, gtt = g[q] * ct;
+        m[0] += grr * cr;
+        m[1] += grr * ct;
+        m[2] += gtt * ct;
+        m[3] += grr * cr * cr;
+        m[4] += grr * cr * ct;
+        m[5] += grr * ct * ct;
+        m[6] += gtt * ct * ct;
+        m[7] += h * grr;
+        m[8] += h * gtt;
+        m[9] += h * grr * cr;
+        m[10] += h * grr * ct;
+        m[11] += h * gtt * ct;
+    }
+#pragma unroll
+    for (int k = 0; k < NONEQ; ++k) out[(size_t)k * ncell + c] = m[k];
+}
+
 // ------------------------------------------------------------ initial state
 // Pressure with noise, rounded exactly as written (no contraction): the
 // same bits as any IEEE implementation of the formula.
@@ -760,6 +823,16 @@ hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, c
             hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
                                step_off);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_noneq(const SolveDesc &d, int cur, bool fp32, double *out, hipStream_t st)
+{
+    const int nb = cell_blocks(d.nr, d.nt);
+    if (fp32)
+        hipLaunchKernelGGL(k_noneq<float>, dim3(nb), dim3(BLOCK), 0, st, d, cur, out);
+    else
+        hipLaunchKernelGGL(k_noneq<double>, dim3(nb), dim3(BLOCK), 0, st, d, cur, out);
     return hipGetLastError();
 }
 

@@ -286,6 +286,12 @@ int pdbm_batch_moments(pdbm_batch *b, int32_t i, double *out, pdbm_diag *diag)
     return PDBM_OK;
 }
 
+int pdbm_batch_noneq(pdbm_batch *b, int32_t i, double *out)
+{
+    if (!b || i < 0 || i >= (int32_t)b->solves.size() || !out) return fail(PDBM_EINVAL, "bad batch index or NULL");
+    return noneq_to_host(*b->solves[i], out, b->st);
+}
+
 }  // extern "C"
 
 // ----------------------------------------------------------------- server --

@@ -21,6 +21,10 @@ PDBM_FP64, PDBM_FP32 = 0, 1
 PDBM_QUEUED, PDBM_RUNNING, PDBM_DONE, PDBM_FAILED = 0, 1, 2, 3
 PDBM_ALLOW_CFL = 1
 NQ = 33
+# components of pdbm_noneq's output (Sec. II.E), in order
+NONEQ_NAMES = ("D2_rr", "D2_rt", "D2_tt", "D3_rrr", "D3_rrt", "D3_rtt", "D3_ttt",
+               "D31_r", "D31_t", "D42_rr", "D42_rt", "D42_tt")
+PDBM_NONEQ_N = len(NONEQ_NAMES)
 
 
 class pdbm_params(C.Structure):
@@ -96,6 +100,9 @@ def lib():
             "pdbm_step_count": (C.c_int64, [vp]),
             "pdbm_moments": (C.c_int, [vp, dp, C.POINTER(pdbm_diag)]),
             "pdbm_moments_async": (C.c_int, [vp, vp]),
+            "pdbm_noneq": (C.c_int, [vp, dp]),
+            "pdbm_noneq_async": (C.c_int, [vp, vp]),
+            "pdbm_batch_noneq": (C.c_int, [vp, C.c_int32, dp]),
             "pdbm_diag_history": (C.c_int, [vp, C.POINTER(pdbm_diag), C.c_int32, C.POINTER(C.c_int32)]),
             "pdbm_read_f": (C.c_int, [vp, dp, dp]),
             "pdbm_write_f": (C.c_int, [vp, dp, dp, C.c_int64]),
@@ -250,6 +257,24 @@ class Solver:
 
     moments_async = pdbm_moments_async
 
+    def pdbm_noneq(self) -> np.ndarray:
+        """Non-equilibrium measures [12][nr][ntheta] (Sec. II.E), components
+        in the order of NONEQ_NAMES."""
+        out = np.empty((PDBM_NONEQ_N, self.nr, self.nt))
+        _check(self.L.pdbm_noneq(self.h, _dptr(out)))
+        return out
+
+    noneq = pdbm_noneq
+
+    def pdbm_noneq_async(self, out_tensor):
+        """Enqueues the non-equilibrium measures into a caller-owned float64
+        device tensor of shape [12][nr][ntheta]."""
+        assert (out_tensor.is_cuda and out_tensor.is_contiguous()
+                and out_tensor.numel() == PDBM_NONEQ_N * self.nr * self.nt)
+        _check(self.L.pdbm_noneq_async(self.h, C.c_void_p(int(out_tensor.data_ptr()))))
+
+    noneq_async = pdbm_noneq_async
+
     def pdbm_diag_history(self, cap: int = 4096):
         buf = (pdbm_diag * cap)()
         n = C.c_int32(0)
@@ -332,6 +357,14 @@ class Batch:
         return out, d.as_dict()
 
     moments = pdbm_batch_moments
+
+    def pdbm_batch_noneq(self, i: int) -> np.ndarray:
+        nr, nt = self.shapes[i]
+        out = np.empty((PDBM_NONEQ_N, nr, nt))
+        _check(self.L.pdbm_batch_noneq(self.h, int(i), _dptr(out)))
+        return out
+
+    noneq = pdbm_batch_noneq
 
 
 class Server:

@@ -1,0 +1,123 @@
+"""Non-equilibrium measures Delta*_m (Sec. II.E) on the GPU, through the C ABI,
+against the CPU oracle and against the two-beam closed form.
+
+Delta*_m are small differences of large moments, so the error is measured
+against the size of the moments themselves: max|D_gpu - D_oracle| over cells,
+divided by max(rho T) for Delta*_2, max(rho T^1.5) for Delta*_3 and
+Delta*_{3,1}, and max(rho T^2) for Delta*_{4,2}."""
+import math
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_0653_amd import pdbm as P
+from paper_1308_0653_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+GROUP = np.array([2, 2, 2, 3, 3, 3, 3, 3, 3, 4, 4, 4])  # moment order that sets each component's scale
+
+
+def _params(w, precision=P.PDBM_FP64):
+    return P.make_params(**w.params_kw(), precision=precision)
+
+
+def _oracle(w, nsteps):
+    o = O.Solver(O.make_params(**w.params_kw()))
+    o.init_ic(**w.ic_kw())
+    o.step(nsteps)
+    return o
+
+
+def _scaled_errors(got, ref, fields):
+    rho, T = fields[0], fields[3]
+    scale = {2: (rho * T).max(), 3: (rho * T ** 1.5).max(), 4: (rho * T ** 2).max()}
+    return np.array([np.abs(got[m] - ref[m]).max() / scale[GROUP[m]] for m in range(P.PDBM_NONEQ_N)])
+
+
+CASES = {
+    "annulus64": W.small_fp64(),
+    "disc": replace(W.small_fp64(), nr=16, ntheta=16, r_min=0.0, r_max=1.0, dt=2e-4, tau=4e-4, r_split=0.3,
+                    nsteps=40),
+    "sector3": replace(W.small_fp64(), nr=24, ntheta=24, sector=3, r_min=0.5, dt=1e-4, tau=4e-4, r_split=0.7,
+                       nsteps=60),
+    "ragged": replace(W.small_fp64(), nr=37, ntheta=71, nsteps=80),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_noneq_parity_with_oracle(case):
+    w = CASES[case]
+    s = P.Solver(_params(w), P.make_ic(**w.ic_kw()))
+    s.step(w.nsteps)
+    got = s.noneq()
+    o = _oracle(w, w.nsteps)
+    ref = o.noneq()
+    err = _scaled_errors(got, ref, o.fields())
+    print(case, dict(zip(P.NONEQ_NAMES, (f"{e:.1e}" for e in err))), flush=True)
+    assert err.max() < TOL64
+    # the run is out of equilibrium somewhere
+    assert np.abs(ref[0]).max() > 1e-6 * (o.fields()[0] * o.fields()[3]).max()
+
+
+def test_noneq_two_beam_mixture_on_gpu():
+    """Every cell holds a mixture of two equilibria drifting at +-d about
+    its mean flow; Delta*_m then has a closed form (Delta*_2 = rho (d d -
+    |d|^2/2 I), odd orders zero, Delta*_{4,2} = rho (3T d d - 3/2 T |d|^2 I +
+    1/2 |d|^2 d d - 1/2 |d|^4 I))."""
+    rng = np.random.default_rng(21)
+    nr, nt = 5, 40
+    w = replace(W.small_fp64(), nr=nr, ntheta=nt, nsteps=0)
+    dth = 2 * math.pi / nt
+    f = np.empty((33, nr, nt))
+    ref = np.zeros((12, nr, nt))
+    scale = 0.0
+    for ir in range(nr):
+        for jt in range(nt):
+            rho, T = rng.uniform(0.5, 2.0), rng.uniform(0.8, 6.0)
+            ur, ut, dr, dt_ = rng.uniform(-0.5, 0.5, 4)
+            th = (jt + 0.5) * dth
+            f[:, ir, jt] = 0.5 * (O.equilibrium(rho, ur + dr, ut + dt_, T, th) +
+                                  O.equilibrium(rho, ur - dr, ut - dt_, T, th))
+            d = np.array([dr, dt_])
+            d2 = d @ d
+            D2 = rho * (np.outer(d, d) - 0.5 * d2 * np.eye(2))
+            D42 = rho * (3 * T * np.outer(d, d) - 1.5 * T * d2 * np.eye(2) + 0.5 * d2 * np.outer(d, d)
+                         - 0.5 * d2 * d2 * np.eye(2))
+            ref[:, ir, jt] = [D2[0, 0], D2[0, 1], D2[1, 1], 0, 0, 0, 0, 0, 0, D42[0, 0], D42[0, 1], D42[1, 1]]
+            scale = max(scale, rho * (T + d2) ** 2)
+    s = P.Solver(_params(w))
+    s.write_f(f, np.zeros((nr, nt)))
+    got = s.noneq()
+    assert np.abs(got - ref).max() < TOL64 * scale
+
+
+def test_noneq_fp32_solver_error_bound():
+    """The FP32 form (f in float32, measures summed in float64) stays within
+    1e-4 of the oracle in the same scaled norm after 200 steps."""
+    w = W.small_fp64()
+    s = P.Solver(_params(w, P.PDBM_FP32), P.make_ic(**w.ic_kw()))
+    s.step(w.nsteps)
+    o = _oracle(w, w.nsteps)
+    err = _scaled_errors(s.noneq(), o.noneq(), o.fields())
+    print("fp32", dict(zip(P.NONEQ_NAMES, (f"{e:.1e}" for e in err))), flush=True)
+    assert err.max() < 1e-4
+
+
+def test_noneq_batch_member_and_async_match_solo():
+    torch = pytest.importorskip("torch")
+    ws = [replace(W.small_fp64(), nr=20 + 7 * k, ntheta=30 + 11 * k, seed=k, nsteps=25) for k in range(3)]
+    b = P.Batch([_params(w) for w in ws], [P.make_ic(**w.ic_kw()) for w in ws], chunk_steps=5)
+    b.step(25)
+    for i, w in enumerate(ws):
+        solo = P.Solver(_params(w), P.make_ic(**w.ic_kw()))
+        solo.step(25)
+        D = solo.noneq()
+        assert np.array_equal(b.noneq(i), D)
+        t = torch.empty((P.PDBM_NONEQ_N, w.nr, w.ntheta), dtype=torch.float64, device="cuda")
+        solo.noneq_async(t)
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), D)
