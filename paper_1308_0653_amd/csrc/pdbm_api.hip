@@ -24,7 +24,9 @@ constexpr int64_t MAX_CELLS = int64_t(1) << 24;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int pitch_of(int nt) { return nt <= 16 ? nt : (nt + 31) / 32 * 32; }
+// Padded row length: a multiple of the 64 columns of one wavefront, so that
+// every wavefront's store of one velocity plane covers whole cache lines.
+int pitch_of(int nt) { return nt <= 16 ? nt : (nt + STRIP - 1) / STRIP * STRIP; }
 
 bool is_fin(double x) { return std::isfinite(x); }
 

@@ -15,7 +15,7 @@ constexpr int HIST_CAP = 4096;  // drift reports kept per solve
 constexpr int PART_RING = PDBM_MAX_CHUNK;  // records whose partial sums may wait to be added up
 constexpr int NXCD = 8;         // accelerator complex dies of an MI355X
 constexpr int NONEQ = PDBM_NONEQ_N;  // components of the non-equilibrium measures
-constexpr int STRIP = 62;       // theta columns stored per wavefront (64 lanes minus 2 halo lanes)
+constexpr int STRIP = 64;       // theta columns stored per wavefront, one per lane
 
 // Per-solve state in device memory written by the host.
 struct SolveState {

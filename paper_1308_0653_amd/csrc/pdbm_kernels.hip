@@ -281,22 +281,33 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x)
     return x;
 }
 
-// A wavefront owns a strip of STRIP consecutive theta columns plus one halo
-// column on each side (lanes 0 and 63), and marches outward (or inward) over
-// a block of rows.  The row being computed and the next two in marching order
-// are held in registers, the row behind in a lane-private LDS slot: radial
-// neighbours come from there, azimuthal ones from the adjacent lanes, so each
-// f value is read from memory once per step (plus the halo columns and the
-// two rows bounding the block).  The second row ahead is requested a whole
-// row of compute before it is first needed.
+// A wavefront owns a strip of 64 consecutive theta columns, one per lane, and
+// marches outward (or inward) over a block of rows.  The row being computed
+// and the next two in marching order are held in registers, the row behind
+// in a lane-private LDS slot: radial neighbours come from there, azimuthal
+// ones from the adjacent lanes, so each f value is read from memory once per
+// step (plus the two rows bounding the block).  The azimuthal neighbours of
+// lanes 0 and 63 (the halo columns, owned by the adjacent strips) come from
+// three gathered loads per row, lane q of which fetches one (plane, side)
+// pair, and are moved into lane 0 or 63 by readlane.  Strips start on
+// 64-column boundaries and rows are padded to a multiple of 64, so every
+// store of a velocity plane covers whole cache lines.  The second row ahead
+// is requested a whole row of compute before it is first needed.
 template <typename real, bool ROT>
 struct Strip {
     DescPtr dp;
     __amdgpu_buffer_rsrc_t fin, fout, lin, lout;
     uint32_t vo, vol;     // byte offsets of this lane's column in f and lambda rows
+    uint32_t vh1, vh2, vhl;  // byte offsets of this lane's halo gathers (plane and column)
     uint32_t row_bytes, lrow_bytes, plane_bytes;
     int lane, pc, rot;    // physical column, direction shift of this lane's data
     bool useful;
+
+    // memory plane of velocity q for data whose direction index is shifted by r
+    static __device__ __forceinline__ int plane_of(int q, int r)
+    {
+        return q == 0 ? 0 : 1 + 8 * ((q - 1) / 8) + ((((q - 1) % 8) + r) & 7);
+    }
 
     __device__ __forceinline__ Strip(DescPtr dp_, const StepBufs &b, int strip) : dp(dp_)
     {
@@ -304,18 +315,35 @@ struct Strip {
         fout = rsrc_of(b.f_out);
         lin = rsrc_of(b.lam_in);
         lout = rsrc_of(b.lam_out);
-        const int nt = dp->nt;
+        const int nt = dp->nt, sec = dp->sector;
         lane = threadIdx.x & 63;
-        const int col = strip * STRIP - 1 + lane;
-        const int wraps = col < 0 ? -1 : col / nt;  // periodic images of the sector
+        const int c0 = strip * STRIP;
+        const int col = c0 + lane;
+        // lanes past the last column hold periodic images of the first ones
+        const int wraps = col / nt;
         pc = col - wraps * nt;
-        rot = ROT ? ((-wraps * dp->sector) & 7) : 0;
-        useful = lane >= 1 && lane <= STRIP && col < nt;
+        rot = ROT ? ((-wraps * sec) & 7) : 0;
+        useful = col < nt;
         vo = (uint32_t)pc * (uint32_t)sizeof(real);
         vol = (uint32_t)pc * 8u;
         row_bytes = (uint32_t)dp->rstride * (uint32_t)sizeof(real);
         lrow_bytes = (uint32_t)dp->pitch * 8u;
         plane_bytes = (uint32_t)dp->plane * (uint32_t)sizeof(real);
+        // halo columns: c0 - 1 (0 <= c0 < nt) and c0 + 64, as periodic images
+        const int cl = c0 == 0 ? nt - 1 : c0 - 1;
+        const int rl = ROT && c0 == 0 ? (sec & 7) : 0;
+        const int wr = (c0 + STRIP) / nt;
+        const int cr = c0 + STRIP - wr * nt;
+        const int rr = ROT ? ((-wr * sec) & 7) : 0;
+        // gather 1: lanes 0..32 left halo of planes 0..32, lanes 33..63 right
+        // halo of planes 0..30; gather 2: lanes 0, 1 right halo of planes 31,
+        // 32; lambda gather: lane 0 left, lane 1 right (other lanes repeat a
+        // valid address)
+        const int es = (int)sizeof(real);
+        vh1 = lane <= 32 ? (uint32_t)(plane_of(lane, rl) * dp->plane + cl) * es
+                         : (uint32_t)(plane_of(lane - 33, rr) * dp->plane + cr) * es;
+        vh2 = lane < 2 ? (uint32_t)(plane_of(31 + lane, rr) * dp->plane + cr) * es : (uint32_t)cl * es;
+        vhl = lane == 1 ? (uint32_t)cr * 8u : (uint32_t)cl * 8u;
     }
 
     __device__ __forceinline__ void load_row(int row, real f[NQ], double &lam) const
@@ -325,10 +353,7 @@ struct Strip {
             // this lane's data of direction dir lives in plane (dir + rot) % 8
             bload(f[0], fin, vo, so);
 #pragma unroll
-            for (int q = 1; q < NQ; ++q) {
-                const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8;
-                bload(f[q], fin, vo + (uint32_t)(base + ((dir + rot) & 7)) * plane_bytes, so);
-            }
+            for (int q = 1; q < NQ; ++q) bload(f[q], fin, vo + (uint32_t)plane_of(q, rot) * plane_bytes, so);
         } else {
             bload(f[0], fin, vo, so);
 #pragma unroll
@@ -339,7 +364,39 @@ struct Strip {
         }
         bload(lam, lin, vol, (uint32_t)row * lrow_bytes);
     }
+
+    // The halo values of row `row`: h[0], h[1] for f, h[2] for lambda.
+    __device__ __forceinline__ void load_halo(int row, real h[2], double &hl) const
+    {
+        const uint32_t so = (uint32_t)row * row_bytes;
+        bload(h[0], fin, vh1, so);
+        bload(h[1], fin, vh2, so);
+        bload(hl, lin, vhl, (uint32_t)row * lrow_bytes);
+    }
 };
+
+// Wave-uniform copy of lane l of v.
+__device__ __forceinline__ float lane_value(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// Halo of plane q from the two f gathers: left neighbour of lane 0, right
+// neighbour of lane 63.
+template <typename real>
+__device__ __forceinline__ real halo_left(const real h[2], int q)
+{
+    return lane_value(h[0], q);
+}
+template <typename real>
+__device__ __forceinline__ real halo_right(const real h[2], int q)
+{
+    return q <= 30 ? lane_value(h[0], 33 + q) : lane_value(h[1], q - 31);
+}
 
 // One row of one strip: moments, F_k(T), f^eq, BGK + chemical term, Cochran
 // lambda, donor-cell fluxes of f and lambda.  fc: row i.  Marching outward
@@ -349,7 +406,8 @@ struct Strip {
 // opposite dd+4 takes the other side).
 template <typename real, bool ROT>
 __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, real (*prev)[64], const real fc[NQ],
-                                           const real fn[NQ], double lbehind, double lc, double lahead,
+                                           const real fn[NQ], const real hf[2], double hlam, double lbehind,
+                                           double lc, double lahead,
                                            const bool mr[4], const bool mt[4], const real acr[4], const real ctv[4],
                                            bool lr_behind, double csx, double csy, double red[5], bool diag)
 {
@@ -423,9 +481,13 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
                 prev[q][lane] = x;
                 const bool rb = sgn == 0 ? mr[dd] : !mr[dd];
                 const real nbr = rb ? behind : fn[q];
-                // both shifts are taken by every lane (a DPP read of a lane
-                // switched off by a branch would return 0), then selected
-                const real left = from_left(x), right = from_right(x);
+                // both shifts and both halo values are taken by every lane
+                // (a DPP read of a lane switched off by a branch would return
+                // 0), then selected; lanes 0 and 63 take the halo columns
+                const real sl = from_left(x), sr = from_right(x);
+                const real hl = halo_left(hf, q), hr = halo_right(hf, q);
+                const real left = lane == 0 ? hl : sl;
+                const real right = lane == 63 ? hr : sr;
                 const bool tl = sgn == 0 ? mt[dd] : !mt[dd];
                 const real nbt = tl ? left : right;
                 const real out = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
@@ -444,7 +506,10 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
         const double q1 = (1.0 - lc) * exp(-(a + b) * dp->dt);
         lreac = 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
     }
-    const double lleft = from_left(lc), lright = from_right(lc);
+    const double sll = from_left(lc), slr = from_right(lc);
+    const double hll = lane_value(hlam, 0), hlr = lane_value(hlam, 1);
+    const double lleft = lane == 0 ? hll : sll;
+    const double lright = lane == 63 ? hlr : slr;
     const double lr = (urp >= 0.0) == lr_behind ? lbehind : lahead;
     const double lt = utp >= 0.0 ? lleft : lright;
     const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
@@ -502,8 +567,9 @@ __device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int stri
     const int step = down ? -1 : 1;
     const int first = down ? i1 - 1 : i0;
     const int count = i1 - i0;
-    real fc[NQ], fn[NQ], fnn[NQ];
-    double lp, lc, ln, lnn;
+    real fc[NQ], fn[NQ], fnn[NQ], hc[2], hn[2];
+    double lp, lc, ln, lnn, hlc, hln;
+    S.load_halo(first, hc, hlc);
     S.load_row(first, fc, lc);
     row_or_ghost(S, first + step, fn, ln, fc, lc);
     row_or_ghost(S, first - step, fnn, lp, fc, lc);  // the row behind the first
@@ -511,13 +577,19 @@ __device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int stri
     for (int q = 0; q < NQ; ++q) prev[q][lane] = fnn[q];
     int ir = first;
     for (int n = 0; n < count; ++n, ir += step) {
+        // the next row computed is always inside the block (never a ghost)
+        if (n + 1 < count) S.load_halo(ir + step, hn, hln);
         row_or_ghost(S, ir + 2 * step, fnn, lnn, fn, ln);
-        update_row<real, ROT>(S, ir, prev, fc, fn, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, red, diag);
+        update_row<real, ROT>(S, ir, prev, fc, fn, hc, hlc, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, red,
+                              diag);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             fc[q] = fn[q];
             fn[q] = fnn[q];
         }
+        hc[0] = hn[0];
+        hc[1] = hn[1];
+        hlc = hln;
         lp = lc;
         lc = ln;
         ln = lnn;

@@ -31,3 +31,44 @@ def test_host_and_device_kernel_names_match(src):
         if not dev_kernels:
             pytest.skip("no kernels in this source")
         assert host_kernels == dev_kernels, (host_kernels ^ dev_kernels)
+
+
+def _kernel_bodies(asm: str, key: str):
+    for name in re.findall(r"^(_Z\S*" + key + r"\S*):", asm, flags=re.M):
+        i = asm.index(name + ":")
+        yield name, asm[i:asm.index(".Lfunc_end", i)].split("\n")
+
+
+def test_step_kernel_takes_lane_shifts_with_every_lane_active():
+    """The step kernel's azimuthal neighbours come from DPP whole-wave lane
+    shifts.  A shift executed while some lanes are switched off (inside a
+    divergent branch) reads 0 from those lanes, silently corrupting their
+    neighbours' update; the source takes every shift unconditionally and
+    selects afterwards.  Checked on the gfx950 assembly: no DPP shift of
+    k_step sits between an exec-narrowing instruction and the matching
+    restore."""
+    src = os.path.join(B.CSRC, "pdbm_kernels.hip")
+    with tempfile.TemporaryDirectory() as tmp:
+        out = os.path.join(tmp, "k.s")
+        cmd = [B.HIPCC, *[f for f in B.FLAGS if f not in ("-shared", "-fPIC")], f"-I{B.INCLUDE}", f"-I{B.CSRC}",
+               "--cuda-device-only", "-S", src, "-o", out]
+        subprocess.run(cmd, cwd=tmp, check=True, capture_output=True)
+        asm = open(out).read()
+    bodies = list(_kernel_bodies(asm, "k_step"))
+    assert len(bodies) == 4
+    for name, lines in bodies:
+        depth, shifts, narrowed = 0, 0, 0
+        for line in lines:
+            t = line.strip()
+            # an if (or the then-arm of an if/else) opens with
+            # s_and_saveexec; the else-arm's s_or_saveexec shares the same
+            # closing restore
+            if t.startswith("s_and_saveexec_b64"):
+                depth += 1
+            elif t.startswith("s_or_b64 exec, exec,"):
+                depth = max(0, depth - 1)
+            if "wave_shr:1" in t or "wave_shl:1" in t:
+                shifts += 1
+                narrowed += depth > 0
+        assert shifts >= 66, (name, shifts)
+        assert narrowed == 0, (name, narrowed)
