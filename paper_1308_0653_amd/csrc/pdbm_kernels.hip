@@ -212,8 +212,10 @@ __device__ __forceinline__ void diag_cell(double v[5], double rho, double ux, do
 // lane-1 (from_left) and by lane+1 (from_right).  Lanes 0 / 63 receive 0; they
 // are halo lanes whose results are never stored.  Call these only where every
 // lane of the wavefront is active (never inside a divergent branch).
-__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+// bound_ctrl set: the lane shifted in from outside the wavefront reads 0, so
+// the instruction needs no prior value of its destination.
+__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
 __device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
 __device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
 __device__ __forceinline__ double from_left(double v)
@@ -465,6 +467,11 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
         const real rF = rho * F[k];
         const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
         const int base = 1 + 8 * (k - 1);
+        // the ring's new values, stored together under one lane mask (in
+        // halves where the rotated sector's per-lane plane offsets already
+        // hold registers)
+        constexpr int G = ROT ? 2 : 4;  // directions dd per store group
+        real o[8];
 #pragma unroll
         for (int dd = 0; dd < 4; ++dd) {
             const real z = v * EP.w(dd);
@@ -490,9 +497,15 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
                 const real right = lane == 63 ? hr : sr;
                 const bool tl = sgn == 0 ? mt[dd] : !mt[dd];
                 const real nbt = tl ? left : right;
-                const real out = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
-                // stored lanes are never rotated sector images
-                if (store) bstore(out, S.fout, S.vo, rowoff + (uint32_t)q * pb);
+                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+            }
+            // stored lanes are never rotated sector images
+            if (dd % G == G - 1 && store) {
+#pragma unroll
+                for (int e = dd + 1 - G; e <= dd; ++e) {
+                    bstore(o[e], S.fout, S.vo, rowoff + (uint32_t)(base + e) * pb);
+                    bstore(o[e + 4], S.fout, S.vo, rowoff + (uint32_t)(base + e + 4) * pb);
+                }
             }
         }
     }
@@ -567,19 +580,23 @@ __device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int stri
     const int step = down ? -1 : 1;
     const int first = down ? i1 - 1 : i0;
     const int count = i1 - i0;
-    real fc[NQ], fn[NQ], fnn[NQ], hc[2], hn[2];
-    double lp, lc, ln, lnn, hlc, hln;
-    S.load_halo(first, hc, hlc);
+    // halos of a row are gathered right after its main loads, when the
+    // adjacent strips fetch the same lines (they then hit in L2)
+    real fc[NQ], fn[NQ], fnn[NQ], hc[2], hn[2], hnn[2];
+    double lp, lc, ln, lnn, hlc, hln, hlnn;
     S.load_row(first, fc, lc);
+    S.load_halo(first, hc, hlc);
     row_or_ghost(S, first + step, fn, ln, fc, lc);
+    if (count > 1) S.load_halo(first + step, hn, hln);
     row_or_ghost(S, first - step, fnn, lp, fc, lc);  // the row behind the first
 #pragma unroll
     for (int q = 0; q < NQ; ++q) prev[q][lane] = fnn[q];
     int ir = first;
     for (int n = 0; n < count; ++n, ir += step) {
-        // the next row computed is always inside the block (never a ghost)
-        if (n + 1 < count) S.load_halo(ir + step, hn, hln);
-        row_or_ghost(S, ir + 2 * step, fnn, lnn, fn, ln);
+        // the second row ahead is the radial neighbour of the next row
+        // computed, if there is one; rows computed are never ghosts
+        if (n + 1 < count) row_or_ghost(S, ir + 2 * step, fnn, lnn, fn, ln);
+        if (n + 2 < count) S.load_halo(ir + 2 * step, hnn, hlnn);
         update_row<real, ROT>(S, ir, prev, fc, fn, hc, hlc, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, red,
                               diag);
 #pragma unroll
@@ -590,6 +607,9 @@ __device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int stri
         hc[0] = hn[0];
         hc[1] = hn[1];
         hlc = hln;
+        hn[0] = hnn[0];
+        hn[1] = hnn[1];
+        hln = hlnn;
         lp = lc;
         lc = ln;
         ln = lnn;

@@ -72,3 +72,24 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
                 narrowed += depth > 0
         assert shifts >= 66, (name, shifts)
         assert narrowed == 0, (name, narrowed)
+
+
+def test_step_kernel_uses_no_scratch_memory():
+    """Register spills of the step kernel must stay in registers (AGPRs): a
+    spill to scratch memory inside the row loop adds memory round trips to
+    every row.  Checked on the code-object metadata of every variant."""
+    src = os.path.join(B.CSRC, "pdbm_kernels.hip")
+    with tempfile.TemporaryDirectory() as tmp:
+        out = os.path.join(tmp, "k.s")
+        cmd = [B.HIPCC, *[f for f in B.FLAGS if f not in ("-shared", "-fPIC")], f"-I{B.INCLUDE}", f"-I{B.CSRC}",
+               "--cuda-device-only", "-S", src, "-o", out]
+        subprocess.run(cmd, cwd=tmp, check=True, capture_output=True)
+        asm = open(out).read()
+    seen = 0
+    for block in asm.split("- .agpr_count:")[1:]:
+        name = re.search(r"\.name:\s+(\S+)", block).group(1)
+        if "k_step" not in name:
+            continue
+        seen += 1
+        assert int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1)) == 0, name
+    assert seen == 4
