@@ -1,0 +1,158 @@
+"""The paper's own experiments on the GPU (FP64, through the C ABI).
+
+Sec. III.B.1: the steady detonation at the paper's resolution runs at the
+CJ speed and leaves the CJ state behind it.  Sec. III.C: the implosion on
+the 1/8-sector disc (with the disc-centre rule) matches the oracle and shows
+the paper's behaviour.  Sec. III.D: the explosion with a small ignition
+region dies out, with a large one it initiates a detonation.  The disc runs
+exceed the donor-cell Courant bound in the innermost cells (as the paper's
+parameters do) and use PDBM_ALLOW_CFL.  Setups are the printed ones
+(tests/golden/paper_values.json)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_0653_amd import pdbm as P
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+TOL64 = 1e-10
+SHOCKED = GOLD["shocked_state"]["value"]
+UNBURNT = [1.0, 1.0, 0.0, 0.0, 0.0]
+
+
+def _shocked(sign):
+    return [SHOCKED["rho"], SHOCKED["T"], sign * SHOCKED["u_r_abs"], 0.0, 1.0]
+
+
+def _disc(nr, R, w1, w2, dt, tau):
+    kw = dict(nr=nr, ntheta=1, r_min=0.0, r_max=R, dt=dt, tau=tau, w1=w1, w2=w2, m=1, n=1, Q=1.0, T_th=1.1,
+              sector=1)
+    return kw
+
+
+def _gpu(kw, ic, flags=P.PDBM_ALLOW_CFL):
+    return P.Solver(P.make_params(**kw, precision=P.PDBM_FP64, flags=flags), P.make_ic(**ic))
+
+
+def _oracle(kw, ic):
+    o = O.Solver(O.make_params(**kw))
+    o.init_ic(ic["r_split"], ic["inner"], ic["outer"])
+    return o
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_implosion_matches_oracle_and_paper():
+    st = GOLD["implosion_setup"]["value"]
+    kw = _disc(st["nr"], st["r_max"], st["w1"], st["w2"], st["dt"], st["tau"])
+    ic = dict(r_split=st["r_split"], inner=UNBURNT, outer=_shocked(-1.0))
+    s, o = _gpu(kw, ic), _oracle(kw, ic)
+    for t in (0.0375, 0.0425, 0.05):
+        n = int(round(t / st["dt"]))
+        s.step(n - s.step_count)
+        o.step(n - o.step_count)
+        F, _ = s.moments()
+        R = o.fields()
+        for k in (0, 1, 3, 5):
+            assert _rel(F[k], R[k]) < TOL64, (t, k)
+        D = s.noneq()
+        assert np.abs(D - o.noneq()).max() < TOL64 * (R[0] * R[3] ** 2).max()
+        # the disc centre stays in equilibrium (Sec. III.C)
+        assert abs(D[0][0, 0]) < 1e-2 * np.abs(D[0]).max(), t
+    # the converging wave has reached the centre: temperature and pressure
+    # peak there and the gas at the centre is compressed (the reflected
+    # shock already carries the density maximum outward by t = 0.05)
+    for k in (3, 4):
+        assert np.argmax(F[k][:, 0]) <= 1, k
+    assert F[0][0, 0] > 2.0
+
+
+def test_explosion_small_ignition_dies_out():
+    """Sec. III.D, R1 = 0.015: the initial energy does not trigger a
+    detonation; the disturbance wave spreads and decays."""
+    setup = GOLD["explosion_setups"]
+    c, e = setup["common"], setup["value"][0]
+    kw = _disc(e["nr"], e["R"], c["w1"], c["w2"], c["dt"], c["tau"])
+    ic = dict(r_split=e["R1"], inner=_shocked(1.0), outer=UNBURNT)
+    s, o = _gpu(kw, ic), _oracle(kw, ic)
+    n0 = int(round(0.005 / c["dt"]))
+    s.step(n0)
+    o.step(n0)
+    F, _ = s.moments()
+    R = o.fields()
+    for k in (0, 1, 3, 5):
+        assert _rel(F[k], R[k]) < TOL64, k
+    r = (np.arange(e["nr"]) + 0.5) * e["R"] / e["nr"]
+    peaks, departure = [], []
+    for t in (0.005, 0.05, 0.15):
+        s.step(int(round(t / c["dt"])) - s.step_count)
+        F, _ = s.moments()
+        D = s.noneq()
+        burnt = r[F[5][:, 0] > 0.5]
+        assert burnt.max() < 1.7 * e["R1"], t  # the burnt region barely grows
+        peaks.append(F[4].max())
+        departure.append(np.abs(D[0]).max())
+    assert peaks[0] > peaks[1] > peaks[2] > 1.0
+    assert departure[0] > departure[1] > departure[2]
+    assert F[3].max() < 1.1  # the wave no longer heats past the ignition temperature
+
+
+def test_explosion_large_ignition_initiates_detonation():
+    """Sec. III.D, R1 = 0.05: direct initiation; the burnt region grows
+    behind a strengthening front."""
+    setup = GOLD["explosion_setups"]
+    c, e = setup["common"], setup["value"][2]
+    kw = _disc(e["nr"], e["R"], c["w1"], c["w2"], c["dt"], c["tau"])
+    ic = dict(r_split=e["R1"], inner=_shocked(1.0), outer=UNBURNT)
+    s = _gpu(kw, ic)
+    r = (np.arange(e["nr"]) + 0.5) * e["R"] / e["nr"]
+    fronts, peaks = [], []
+    for t in (0.025, 0.25):
+        s.step(int(round(t / c["dt"])) - s.step_count)
+        F, _ = s.moments()
+        lam = F[5][:, 0]
+        front = r[lam > 0.5].max()
+        print("t", t, "front", front, "min lambda behind", lam[r < 0.8 * front].min(), "p max", F[4].max(), flush=True)
+        assert lam[r < 0.8 * front].min() > 0.97, t  # burnt (the reaction still completing) behind the front
+        fronts.append(front)
+        peaks.append(F[4].max())
+    assert fronts[1] > 8 * e["R1"]
+    assert peaks[1] > peaks[0]
+
+
+def test_steady_detonation_at_paper_resolution():
+    """Sec. III.B.1 at the printed resolution (Nr = 20000, dt = 2.5e-7, to
+    t = 0.025): the detonation runs within 3 % of the CJ speed and the
+    state behind it is within 1 % of the paper's simulated state."""
+    st = GOLD["vv_setup"]["value"]
+    cj = GOLD["cj_state"]["value"]
+    kw = dict(nr=st["nr"], ntheta=1, r_min=st["r_min"], r_max=st["r_max"], dt=st["dt"], tau=st["tau"], w1=st["w1"],
+              w2=st["w2"], m=1, n=1, Q=1.0, T_th=1.1, sector=8)
+    ic = dict(r_split=st["r_split"], inner=[cj["rho"], cj["T"], cj["u_r"], 0.0, 1.0], outer=UNBURNT)
+    s = _gpu(kw, ic, flags=0)
+    r = st["r_min"] + (np.arange(st["nr"]) + 0.5) * (st["r_max"] - st["r_min"]) / st["nr"]
+    ts, xs = [], []
+    nsamp = 40
+    for k in range(1, nsamp + 1):
+        s.step(int(round(k * st["t_end"] / nsamp / st["dt"])) - s.step_count)
+        F, _ = s.moments()
+        lam = F[5][:, 0]
+        i = np.where(lam > 0.5)[0].max()
+        ts.append(s.step_count * st["dt"])
+        xs.append(r[i] + (lam[i] - 0.5) / (lam[i] - lam[i + 1]) * (r[i + 1] - r[i]))
+    h = nsamp // 2
+    speed = np.polyfit(ts[h:], xs[h:], 1)[0]
+    print("detonation speed", speed, "CJ", GOLD["cj_speed"]["value"], flush=True)
+    assert abs(speed / GOLD["cj_speed"]["value"] - 1) < 0.03
+    j = np.searchsorted(r, xs[-1] - 0.01)
+    post = GOLD["lb_post_state"]["value"]
+    assert abs(F[0][j, 0] / post["rho"] - 1) < 0.01
+    assert abs(F[3][j, 0] / post["T"] - 1) < 0.01
+    assert abs(F[1][j, 0] / post["u_r"] - 1) < 0.01
