@@ -21,7 +21,7 @@ int fail(int code, const std::string &msg);
         if (e_ != hipSuccess) return ::pdbm::fail(PDBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int DEFAULT_BATCH_ROWS = 16;  // rows per wavefront in packed launches
+constexpr int DEFAULT_BATCH_ROWS = 4;  // rows per wavefront in packed launches (many rounds of short wavefronts balance best)
 
 // Device memory of one solve, in this order (all offsets 256-byte aligned).
 struct Layout {
