@@ -209,9 +209,9 @@ __device__ __forceinline__ void diag_cell(double v[5], double rho, double ux, do
 
 // ------------------------------------------------------------------ step --
 // Cross-lane moves within a wavefront (DPP wave shifts): the value held by
-// lane-1 (from_left) and by lane+1 (from_right).  Lanes 0 / 63 receive 0; they
-// are halo lanes whose results are never stored.  Call these only where every
-// lane of the wavefront is active (never inside a divergent branch).
+// lane-1 (from_left) and by lane+1 (from_right).  Lanes 0 / 63 receive 0 and
+// take their neighbours from the halo gathers instead.  Call these only where
+// every lane of the wavefront is active (never inside a divergent branch).
 // bound_ctrl set: the lane shifted in from outside the wavefront reads 0, so
 // the instruction needs no prior value of its destination.
 __device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
@@ -263,16 +263,21 @@ __device__ __forceinline__ void bload(double &v, __amdgpu_buffer_rsrc_t r, uint3
     const i32x2 t = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
     v = __hiloint2double(t.y, t.x);
 }
+// Stores are non-temporal (cache policy nt): the new state is not read again
+// in this step, and keeping it out of the caches leaves them to the lines
+// the adjacent strips and row blocks read twice (halo columns, block
+// boundary rows).
+constexpr int STORE_NT = 2;
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, vo, so, STORE_NT);
 }
 __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
 {
     i32x2 t;
     t.x = __double2loint(v);
     t.y = __double2hiint(v);
-    __builtin_amdgcn_raw_buffer_store_b64(t, r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(t, r, vo, so, STORE_NT);
 }
 // Keeps a scalar offset opaque to the optimiser, so that the 33 plane offsets
 // are re-derived by one scalar add each instead of being hoisted out of the
