@@ -1,0 +1,76 @@
+"""Strip and row-block edges of the step kernel against the oracle (FP64).
+
+A wavefront owns 64 theta columns and a block of rows; columns past the last
+one hold periodic images, the two halo columns come from gathers, rows are
+padded to a multiple of 64.  These cases put the last column of the grid at
+every position relative to the strip (widths around 1, 16, 64 and 128), use
+row counts that leave blocks of one or two rows, march blocks in both
+directions, and rotate the halo for a sector."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_0653_amd import pdbm as P
+from paper_1308_0653_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+WIDTHS = [1, 2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 200]
+
+
+def _case(nr, nt, sector=8, seed=0):
+    # a reacting, moving, noisy state: ignition inside r < 0.55
+    return replace(W.small_fp64(), nr=nr, ntheta=nt, r_min=0.3, r_max=1.0, dt=2e-5, tau=5e-5, r_split=0.55,
+                   sector=sector, p_noise=1e-3, seed=seed, nsteps=12)
+
+
+def _scales(R):
+    sc = [np.abs(R[k]).max() for k in range(6)]
+    us = max(sc[1], sc[2], np.sqrt(np.abs(R[3]).max()))
+    sc[1] = sc[2] = us
+    return [v if v > 0 else 1.0 for v in sc]  # a field that is zero everywhere (lambda) is compared absolutely
+
+
+def _check(F, w):
+    o = O.Solver(O.make_params(**w.params_kw()))
+    o.init_ic(**w.ic_kw())
+    o.step(w.nsteps)
+    R = o.fields()
+    sc = _scales(R)
+    err = np.array([np.abs(F[k] - R[k]).max() / sc[k] for k in range(6)])
+    assert np.isfinite(err).all() and err.max() < TOL64, (w.nr, w.ntheta, w.sector, err)
+
+
+@pytest.mark.parametrize("nt", WIDTHS)
+def test_strip_widths_single_solve(nt):
+    for nr in (1, 2, 5, 33):
+        w = _case(nr, nt)
+        s = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64), P.make_ic(**w.ic_kw()))
+        s.step(w.nsteps)
+        F, _ = s.moments(check=False)
+        _check(F, w)
+
+
+def test_strip_widths_packed_short_blocks():
+    """Packed launches use 4-row blocks: every nr below gives a last block
+    of 1, 2 or 3 rows, marched outward or inward by block parity."""
+    ws = [_case(nr, nt, seed=i) for i, (nr, nt) in enumerate([(5, 65), (6, 63), (7, 129), (9, 17), (10, 128),
+                                                              (13, 1), (3, 200)])]
+    b = P.Batch([P.make_params(**w.params_kw(), precision=P.PDBM_FP64) for w in ws],
+                [P.make_ic(**w.ic_kw()) for w in ws], chunk_steps=4)
+    b.step(ws[0].nsteps)
+    for i, w in enumerate(ws):
+        F, _ = b.moments(i, check=False)
+        _check(F, w)
+
+
+@pytest.mark.parametrize("nt,sector", [(65, 1), (130, 3), (17, 5), (64, 2)])
+def test_rotated_sector_halos(nt, sector):
+    w = _case(6, nt, sector=sector)
+    s = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64), P.make_ic(**w.ic_kw()))
+    s.step(w.nsteps)
+    F, _ = s.moments(check=False)
+    _check(F, w)
