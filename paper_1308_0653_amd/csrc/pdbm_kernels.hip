@@ -624,6 +624,164 @@ __device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int stri
     }
 }
 
+// Memory plane of velocity q whose direction index is shifted by r.
+__device__ __forceinline__ int shifted_plane(int q, int r)
+{
+    return q == 0 ? 0 : 1 + 8 * ((q - 1) / 8) + ((((q - 1) % 8) + r) & 7);
+}
+
+// One step of 64 consecutive rows of a solve with a single theta column
+// (ntheta = 1, the quasi-one-dimensional runs of Sec. III): lane l owns row
+// 64 blk + l.  Radial neighbours come from the adjacent lanes (DPP shifts)
+// and, for lanes 0 and 63, from gathers of the rows below and above the
+// block, which apply the radial ghost rules of Sec. II.D.  The azimuthal
+// neighbours of a cell are the cell itself with directions turned by the
+// sector (periodic halo, f_{k,i}(j-1) = f_{k,(i+s)%8}(j) and f_{k,i}(j+1) =
+// f_{k,(i-s)%8}(j)); they are read back from the wavefront's LDS slot.
+// The arithmetic per cell is that of update_row.
+template <typename real>
+__device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, int blk, real (*slot)[64],
+                                             double red[5], bool diag)
+{
+    const int lane = threadIdx.x & 63;
+    const int nr = dp->nr, sec = dp->sector;
+    const int r0 = blk * 64;
+    const int row = r0 + lane;
+    const int re = min(row, nr - 1);  // lanes past the last row hold its zero-gradient image
+    const bool store = row < nr;
+    const __amdgpu_buffer_rsrc_t fin = rsrc_of(bufs.f_in), fout = rsrc_of(bufs.f_out);
+    const __amdgpu_buffer_rsrc_t lin = rsrc_of(bufs.lam_in), lout = rsrc_of(bufs.lam_out);
+    const uint32_t rowb = (uint32_t)dp->rstride * (uint32_t)sizeof(real);
+    const uint32_t pb = (uint32_t)dp->plane * (uint32_t)sizeof(real);
+    const uint32_t lrowb = (uint32_t)dp->pitch * 8u;
+    const uint32_t vo = (uint32_t)re * rowb, vol = (uint32_t)re * lrowb;
+
+    real fc[NQ];
+    double lc;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) bload(fc[q], fin, vo, (uint32_t)q * pb);
+    bload(lc, lin, vol, 0u);
+    // gathers of the row below the block (ghost of row 0 at r_min: a copy,
+    // or at the disc centre row 0 with directions turned by 4) and of the
+    // row above it (clamped: the zero-gradient copy of the last row)
+    const int rlo = r0 == 0 ? 0 : r0 - 1;
+    const int tlo = r0 == 0 && dp->disc ? 4 : 0;
+    const int rhi = min(r0 + 64, nr - 1);
+    const uint32_t vh1 = lane <= 32 ? (uint32_t)rlo * rowb + (uint32_t)shifted_plane(lane, tlo) * pb
+                                    : (uint32_t)rhi * rowb + (uint32_t)(lane - 33) * pb;
+    const uint32_t vh2 = lane < 2 ? (uint32_t)rhi * rowb + (uint32_t)(31 + lane) * pb : (uint32_t)rlo * rowb;
+    const uint32_t vhl = lane == 1 ? (uint32_t)rhi * lrowb : (uint32_t)rlo * lrowb;
+    real hf[2];
+    double hlam;
+    bload(hf[0], fin, vh1, 0u);
+    bload(hf[1], fin, vh2, 0u);
+    bload(hlam, lin, vhl, 0u);
+
+    // (1) moments
+    real rho, jx, jy, e;
+    raw_moments(fc, rho, jx, jy, e);
+    const real irho = (real)1 / rho;
+    const real ux = jx * irho, uy = jy * irho;
+    const real u2 = ux * ux + uy * uy;
+    const real T = e * irho - (real)0.5 * u2;
+    const double Td = (double)T;
+    // (2) weights and f^eq polynomial
+    real F[5];
+    weights(dp->A, Td, F);
+    const EqPoly<real> EP(ux, uy, u2, T);
+    // (3) Cochran rate, gated by the ignition temperature (float64)
+    double a = 0.0, b = 0.0, R = 0.0;
+    const bool on = dp->reacts && Td > dp->T_th;
+    if (on) {
+        const double p = (double)rho * Td;
+        a = dp->w1 * ipow(p, dp->m);
+        b = dp->w2 * ipow(p, dp->n);
+        R = (1.0 - lc) * (a + b * lc);
+    }
+    const real beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
+    const real omega = (real)dp->omega;
+    const real keep = (real)1 - omega;
+    const real Bz = (real)-2 * beta * T;
+
+    // polar components of directions dd = 0..3 at theta_0 (dd+4 is the negative)
+    const double2 cs = dp->cs[0];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    const double ri = dp->r_min + ((double)re + 0.5) * dp->dr;
+    const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
+    real acr[4], act[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        acr[dd] = fabs(crv[dd]) * kr;
+        act[dd] = fabs(ctv[dd]) * kt;
+    }
+    // the cell's distributions, for its rotated azimuthal neighbours
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) slot[q][lane] = fc[q];
+
+    const real rest = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * fc[0];
+    if (store) bstore(rest, fout, vo, 0u);
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real v = (real)speed(k);
+        const real rF = rho * F[k];
+        const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
+        const int base = 1 + 8 * (k - 1);
+        real o[8];
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            const real z = v * EP.w(dd);
+            real pp, pm;
+            EP.eval(z, pp, pm);
+            const real bz = Bz * z;
+#pragma unroll
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const int q = base + dd + 4 * sgn;
+                const real x = fc[q];
+                const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * x : rF * pm * (Ak - bz) + omega * x;
+                // radial upwind (C_r >= 0 takes the row below); every lane
+                // takes both shifts, then selects
+                const real sl = from_left(x), sr = from_right(x);
+                const real hl = halo_left(hf, q), hr = halo_right(hf, q);
+                const real lower = lane == 0 ? hl : sl;
+                const real upper = lane == 63 ? hr : sr;
+                const bool below = sgn == 0 ? crv[dd] >= (real)0 : crv[dd] < (real)0;
+                const real nbr = below ? lower : upper;
+                // azimuthal upwind (C_theta >= 0 takes j-1): this cell with
+                // the direction index turned by +s (j-1) or -s (j+1)
+                const bool left = sgn == 0 ? ctv[dd] >= (real)0 : ctv[dd] < (real)0;
+                const int dir = dd + 4 * sgn;
+                const real nbt = slot[base + ((dir + (left ? sec : 8 - sec)) & 7)][lane];
+                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+            }
+        }
+        if (store) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bstore(o[i], fout, vo, (uint32_t)(base + i) * pb);
+        }
+    }
+
+    // (4) lambda: closed-form Cochran step, then upwind by own-cell u (the
+    // azimuthal neighbour of the single column is the cell itself)
+    const double uxd = (double)ux, uyd = (double)uy;
+    const double urp = uxd * cs.x + uyd * cs.y;
+    double lreac = lc;
+    if (on && a + b > 0.0) {
+        const double q1 = (1.0 - lc) * exp(-(a + b) * dp->dt);
+        lreac = 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
+    }
+    const double sll = from_left(lc), slr = from_right(lc);
+    const double hll = lane_value(hlam, 0), hlr = lane_value(hlam, 1);
+    const double llow = lane == 0 ? hll : sll;
+    const double lup = lane == 63 ? hlr : slr;
+    const double lr = urp >= 0.0 ? llow : lup;
+    const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr);
+    if (store) bstore(lnew, lout, vol, 0u);
+
+    if (diag && store) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lc, ri * dp->dr * dp->dth, dp->Q);
+}
+
 // Occupancy: float32 rows fit two wavefronts per SIMD; float64 rows take
 // the whole register file of one (the next row in flight is 66 VGPRs).
 template <typename real>
@@ -671,11 +829,16 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
     // row-block major: the strips of one row block sit side by side in the
     // same XCD and share their halo columns in its L2; odd row blocks march
     // inward so that the rows bounding two blocks are read by both at once.
-    const int rows = dp->rows, nstrip = dp->nstrip;
-    const int rb = lt / nstrip, strip = lt - rb * nstrip;
-    const int i0 = rb * rows;
-    const int i1 = min(i0 + rows, dp->nr);
-    march<real, ROT>(dp, bufs, strip, i0, i1, (rb & 1) != 0, prev[threadIdx.x >> 6], red, diag);
+    if (dp->nt == 1) {
+        // one theta column: lanes along r
+        radial_block<real>(dp, bufs, lt, prev[threadIdx.x >> 6], red, diag);
+    } else {
+        const int rows = dp->rows, nstrip = dp->nstrip;
+        const int rb = lt / nstrip, strip = lt - rb * nstrip;
+        const int i0 = rb * rows;
+        const int i1 = min(i0 + rows, dp->nr);
+        march<real, ROT>(dp, bufs, strip, i0, i1, (rb & 1) != 0, prev[threadIdx.x >> 6], red, diag);
+    }
     if (diag) {
         const int64_t slot = (step / dp->diag_every) % PART_RING;
         double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
@@ -897,6 +1060,7 @@ int cell_blocks(int nr, int nt) { return (int)(((int64_t)nr * nt + BLOCK - 1) / 
 
 int solve_waves(int nr, int nt, int rows)
 {
+    if (nt == 1) return (nr + STRIP - 1) / STRIP;  // lanes along r: 64 rows per wavefront
     return (int)((int64_t)((nr + rows - 1) / rows) * ((nt + STRIP - 1) / STRIP));
 }
 

@@ -56,20 +56,34 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
         asm = open(out).read()
     bodies = list(_kernel_bodies(asm, "k_step"))
     assert len(bodies) == 4
+    sreg = r"s\[\d+:\d+\]"
     for name, lines in bodies:
-        depth, shifts, narrowed = 0, 0, 0
+        # An exec-narrowing region opens with s_and_saveexec_b64 sX (on every
+        # path that enters it, so possibly more than once in the text) and
+        # closes with s_or_b64 exec, exec, sY where sY holds the saved mask.
+        # The mask may move on the way (s_xor_b64 sA, exec, sX before an
+        # else-arm, s_or_saveexec_b64 / s_andn2_saveexec_b64 sA, sX, s_mov):
+        # each region is the set of registers its mask has been copied to.
+        regions, shifts, narrowed = [], 0, 0
         for line in lines:
             t = line.strip()
-            # an if (or the then-arm of an if/else) opens with
-            # s_and_saveexec; the else-arm's s_or_saveexec shares the same
-            # closing restore
-            if t.startswith("s_and_saveexec_b64"):
-                depth += 1
-            elif t.startswith("s_or_b64 exec, exec,"):
-                depth = max(0, depth - 1)
+            m = re.match(r"s_and_saveexec_b64\s+(" + sreg + ")", t)
+            if m:
+                regions.append({m.group(1)})
+                continue
+            m = re.match(r"s_(?:xor_b64|mov_b64|or_saveexec_b64|andn2_saveexec_b64)\s+(" + sreg + r"),\s*(?:exec,\s*)?("
+                         + sreg + ")", t)
+            if m:
+                for reg in regions:
+                    if m.group(2) in reg:
+                        reg.add(m.group(1))
+                continue
+            m = re.match(r"s_or_b64\s+exec,\s*exec,\s*(" + sreg + ")", t)
+            if m:
+                regions = [reg for reg in regions if m.group(1) not in reg]
             if "wave_shr:1" in t or "wave_shl:1" in t:
                 shifts += 1
-                narrowed += depth > 0
+                narrowed += bool(regions)
         assert shifts >= 66, (name, shifts)
         assert narrowed == 0, (name, narrowed)
 
