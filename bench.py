@@ -83,6 +83,46 @@ def time_solver(P, w, precision, steps, warmup, torch):
     return wall, ev, diag
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "outward1024_golden.npz")
+
+
+def _sig(x, digits=3):
+    return float(f"{float(x):.{digits}g}")
+
+
+def fp32_errors(P, W, torch):
+    """Error of the float32 form on the outward 1024^2 run at steps 500,
+    1000, 2000 (outside the timed region): normwise L_inf and L2 of rho, T,
+    lambda against the float64 GPU field, and L_inf against the oracle's
+    stored samples of the same run (tests/golden, written by the oracle)."""
+    w = W.outward_fp64()
+    stream = torch.cuda.current_stream()
+    s64 = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64), P.make_ic(**w.ic_kw()), stream=stream)
+    s32 = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP32), P.make_ic(**w.ic_kw()), stream=stream)
+    gold = np.load(GOLDEN) if os.path.exists(GOLDEN) else None
+    names = {0: "rho", 3: "T", 5: "lambda"}
+    out = {}
+    for st in (500, 1000, 2000):
+        s64.step(st - s64.step_count)
+        s32.step(st - s32.step_count)
+        F64, _ = s64.moments(check=False)
+        F32, _ = s32.moments(check=False)
+        rec = {}
+        for k, name in names.items():
+            d = F32[k] - F64[k]
+            rec[name] = {"linf": _sig(np.abs(d).max() / np.abs(F64[k]).max()),
+                         "l2": _sig(np.linalg.norm(d) / np.linalg.norm(F64[k]))}
+            if gold is not None and k in list(gold["fields"]):
+                row = list(gold["fields"]).index(k)
+                ref = gold[f"s{st}_vals"][row]
+                rec[name]["linf_vs_oracle"] = _sig(np.abs(F32[k][gold["ir"], gold["jt"]] - ref).max()
+                                                   / gold[f"s{st}_maxabs"][k])
+        out[str(st)] = rec
+    s64.close()
+    s32.close()
+    return out
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the same
@@ -260,7 +300,8 @@ def main():
         wall32, ev32, _ = time_solver(P, w32, P.PDBM_FP32, a.steps, a.warmup, torch)
         out["fp32"] = {"value": round(w32.cells * a.steps / wall32, 1), "unit": "cell-updates/s",
                        "ms_per_step": round(wall32 / a.steps * 1e3, 5), "speedup_vs_f64": round(wall / wall32, 3),
-                       "roofline": roofline(w32.cells, "f32", ev32, a.steps, measured_traffic("k_step_f32"))}
+                       "roofline": roofline(w32.cells, "f32", ev32, a.steps, measured_traffic("k_step_f32")),
+                       "error_vs_fp64": fp32_errors(P, W, torch)}
     if not a.no_serving:
         sweep = packed_sweep(P, W, torch, a.batch_solves, a.batch_steps)
         out["packed_sweep"] = sweep
