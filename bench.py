@@ -61,6 +61,28 @@ def copy_probe(torch):
     print(json.dumps({"copy_probe_bytes_each_way": n, "launches": 5}))
 
 
+def copy_bandwidth(torch):
+    """Read+write bandwidth of a plain 1 GiB device copy on this GPU (GB/s),
+    the practical ceiling the step kernel is compared with beside the
+    vendor peak."""
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / 10
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n / sec / 1e9
+
+
 def time_solver(P, w, precision, steps, warmup, torch):
     """Times `steps` steps after `warmup` untimed ones.  Returns (wall seconds,
     event seconds): the wall clock is bracketed by device synchronisation,
@@ -143,12 +165,19 @@ def measured_traffic(kernel: str):
     return data.get(kernel, {}).get("traffic_bytes")
 
 
-def roofline(cells, dtype, ev_seconds, steps, traffic=None):
+def roofline(cells, dtype, ev_seconds, steps, traffic=None, copy_gbs=None):
     per_launch = BYTES_PER_CELL[dtype] * cells
     achieved = per_launch / (ev_seconds / steps) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "bytes_per_launch": per_launch, "kernel": "k_step", "avg_launch_us": round(ev_seconds / steps * 1e6, 2)}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "bytes_per_launch": per_launch, "kernel": "k_step", "avg_launch_us": round(ev_seconds / steps * 1e6, 2)}
+    if copy_gbs:
+        # against what a plain copy reaches here, algorithmic and measured bytes
+        out["copy_gbs"] = round(copy_gbs, 1)
+        out["frac_of_copy"] = round(achieved / copy_gbs, 4)
+        if traffic:
+            out["traffic_frac_of_copy"] = round(traffic / (ev_seconds / steps) / 1e9 / copy_gbs, 4)
+    return out
 
 
 def packed_sweep(P, W, torch, count, nsteps):
@@ -271,6 +300,7 @@ def main():
     if a.copy_probe:
         copy_probe(torch)
         return
+    copy_gbs = copy_bandwidth(torch)
     w = W.outward_fp64()
     wall, ev, diag = time_solver(P, w, P.PDBM_FP64, a.steps, a.warmup, torch)
     value = w.cells * a.steps / wall
@@ -289,7 +319,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nr": w.nr, "ntheta": w.ntheta, "r": [w.r_min, w.r_max],
                    "cells": w.cells, "diag_every": 1, "parallelism": "single GPU"},
-        "roofline": roofline(w.cells, "f64", ev, a.steps, measured_traffic("k_step_f64")),
+        "roofline": roofline(w.cells, "f64", ev, a.steps, measured_traffic("k_step_f64"), copy_gbs),
         "hbm_frac_of_peak": None,
     }
     out["hbm_frac_of_peak"] = out["roofline"]["frac"]
@@ -300,7 +330,7 @@ def main():
         wall32, ev32, _ = time_solver(P, w32, P.PDBM_FP32, a.steps, a.warmup, torch)
         out["fp32"] = {"value": round(w32.cells * a.steps / wall32, 1), "unit": "cell-updates/s",
                        "ms_per_step": round(wall32 / a.steps * 1e3, 5), "speedup_vs_f64": round(wall / wall32, 3),
-                       "roofline": roofline(w32.cells, "f32", ev32, a.steps, measured_traffic("k_step_f32")),
+                       "roofline": roofline(w32.cells, "f32", ev32, a.steps, measured_traffic("k_step_f32"), copy_gbs),
                        "error_vs_fp64": fp32_errors(P, W, torch)}
     if not a.no_serving:
         sweep = packed_sweep(P, W, torch, a.batch_solves, a.batch_steps)
