@@ -187,3 +187,61 @@ def test_server_shutdown_with_pending_work():
     srv.close()  # must not wait for the 100000-step solves
     assert time.perf_counter() - t0 < 10.0
     assert ids
+
+
+def test_server_admits_arrivals_while_others_run():
+    """Continuous batching, not a queue: a short request that arrives while
+    two long ones are on the GPU is admitted at the next chunk boundary and
+    finishes first, while they keep running."""
+    w = _small_sweep(1, seed=8)[0]
+    p = _params(w, P.PDBM_FP32)
+    srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=4, chunk_steps=10)
+    long_ids = [srv.submit(p, P.make_ic(**replace(w, seed=k).ic_kw()), 20000) for k in range(2)]
+    t0 = time.perf_counter()
+    while srv.stats()["running"] < 2:
+        assert time.perf_counter() - t0 < 30.0
+        time.sleep(0.005)
+    short = srv.submit(p, P.make_ic(**w.ic_kw()), 50, keep_fields=True)
+    assert srv.wait(120.0)
+    ts, tl = srv.times(short), [srv.times(i) for i in long_ids]
+    for t in tl:
+        assert ts[1] > t[1]  # admitted after the long ones started ...
+        assert ts[2] < t[2]  # ... and done before they were
+    state, F, _ = srv.poll(short, fields=True)
+    assert state == P.PDBM_DONE
+    solo = P.Batch([p], [P.make_ic(**w.ic_kw())])
+    solo.step(50)
+    assert np.array_equal(F, solo.moments(0)[0])
+    srv.close()
+
+
+def test_server_submit_from_many_threads():
+    import threading
+    ws = _small_sweep(4, seed=9, nsteps=30)
+    srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=3, chunk_steps=5)
+    ids, errors = [], []
+    lock = threading.Lock()
+
+    def client(k):
+        try:
+            for j in range(4):
+                w = ws[(k + j) % len(ws)]
+                rid = srv.submit(_params(w, P.PDBM_FP32), P.make_ic(**w.ic_kw()), w.nsteps + j)
+                with lock:
+                    ids.append(rid)
+        except Exception as e:  # pragma: no cover - reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors
+    assert srv.wait(60.0)
+    assert len(set(ids)) == 16
+    for rid in ids:
+        assert srv.poll(rid)[0] == P.PDBM_DONE
+    st = srv.stats()
+    assert st["submitted"] == 16 and st["done"] == 16
+    srv.close()
