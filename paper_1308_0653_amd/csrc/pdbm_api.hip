@@ -3,6 +3,7 @@
 // (include/pdbm.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -67,19 +68,23 @@ Layout pdbm::layout_of(const pdbm_params &p, int rows)
 // per SIMD in float64, 2 in float32), so that every wavefront marches the
 // longest possible column and none waits for a second round.
 // PDBM_ROWS_PER_WAVE overrides it (tuning).
-int pdbm::rows_per_wave(int nr, int nt, bool fp32)
+int pdbm::rows_per_wave(const pdbm_params &p)
 {
+    const int nr = p.nr, nt = p.ntheta;
     static const int env = [] {
         const char *e = std::getenv("PDBM_ROWS_PER_WAVE");
         return e ? std::atoi(e) : 0;
     }();
     if (env > 0) return env;
-    const int64_t slots = 256 * 4 * (fp32 ? 2 : 1);
+    // one round of wavefronts: one per SIMD in float64, two in float32
+    const int64_t slots = 256 * 4 * (p.precision == PDBM_FP32 ? 2 : 1);
     const int64_t strips = (nt + STRIP - 1) / STRIP;
     int64_t rows = ((int64_t)nr * strips + slots - 1) / slots;
     if (rows < 2) rows = 2;
     while (strips * ((nr + rows - 1) / rows) > slots) ++rows;
-    return (int)rows;
+    // short enough for the two-step kernel (large grids then run more than
+    // one round of wavefronts)
+    return (int)std::min<int64_t>(rows, FUSE_ROWS);
 }
 
 // Largest |C_r| + |C_theta| over the grid for the fastest speed: the
@@ -173,7 +178,7 @@ int pdbm_state_bytes(const pdbm_params *p, size_t *bytes)
     if (p->nr < 1 || p->ntheta < 1 || (int64_t)p->nr * p->ntheta > MAX_CELLS ||
         (p->precision != PDBM_FP64 && p->precision != PDBM_FP32))
         return fail(PDBM_EINVAL, "bad grid or precision");
-    *bytes = layout_of(*p, rows_per_wave(p->nr, p->ntheta, p->precision == PDBM_FP32)).total;
+    *bytes = layout_of(*p, rows_per_wave(*p)).total;
     return PDBM_OK;
 }
 
@@ -307,6 +312,7 @@ int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_
     }
     HIPCHK(launch_init_ic(hd, 0, fp32, *ic, st));
     step = 0;
+    flip = 0;
     rec_from = 0;
     red_to = 0;
     return PDBM_OK;
@@ -325,9 +331,19 @@ int Solve::set_step(int64_t s, hipStream_t st)
     HIPCHK(hipMemcpyAsync(hd.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     step = s;
+    flip = 0;
     rec_from = s;
     red_to = s;
     return PDBM_OK;
+}
+
+bool Solve::fusable() const
+{
+    static const bool off = [] {
+        const char *e = std::getenv("PDBM_FUSE");
+        return e && e[0] == '0';
+    }();
+    return !off && !fp32 && !rot() && p.ntheta > 1 && L.rows <= FUSE_ROWS;
 }
 
 int Solve::reduce_records(hipStream_t st)
@@ -380,8 +396,7 @@ int pdbm_create(const pdbm_params *p, const pdbm_ic *ic, void *workspace, size_t
     pdbm_solver *h = new (std::nothrow) pdbm_solver;
     if (!h) return fail(PDBM_ENOMEM, "host allocation failed");
     h->st = (hipStream_t)stream;
-    rc = h->s.init(*p, ic, workspace, workspace_bytes, rows_per_wave(p->nr, p->ntheta, p->precision == PDBM_FP32),
-                   INT64_MAX, h->st);
+    rc = h->s.init(*p, ic, workspace, workspace_bytes, rows_per_wave(*p), INT64_MAX, h->st);
     if (rc == PDBM_OK && hipStreamSynchronize(h->st) != hipSuccess) rc = fail(PDBM_EHIP, "initialisation failed");
     if (rc) {
         (void)hipStreamSynchronize(h->st);
@@ -419,9 +434,21 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
 {
     if (!h || nsteps < 0) return fail(PDBM_EINVAL, "bad solver or step count");
     Solve &s = h->s;
-    for (int64_t i = 0; i < nsteps; ++i) {
-        HIPCHK(launch_step(s.dd, nullptr, s.waves(), nullptr, s.step, s.fp32, s.rot(), h->st));
-        if (++s.step - s.red_to >= PART_RING) {
+    const bool pairs = s.fusable();
+    for (int64_t i = 0; i < nsteps;) {
+        if (pairs && nsteps - i >= 2) {
+            HIPCHK(launch_step2(s.dd, s.waves(), s.step, s.flip, s.fp32, h->st));
+            s.step += 2;
+            s.flip ^= 1;
+            i += 2;
+        } else {
+            HIPCHK(launch_step(s.dd, nullptr, s.waves(), nullptr, s.step, s.flip, s.fp32, s.rot(), h->st));
+            s.step += 1;
+            i += 1;
+        }
+        // the partial-sum ring holds PART_RING records: add them up before
+        // the next launch (at most two steps) could overwrite one
+        if (s.step - s.red_to > PART_RING - 2) {
             int rc = s.reduce_records(h->st);
             if (rc) return rc;
         }

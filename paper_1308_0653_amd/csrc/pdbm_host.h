@@ -50,6 +50,7 @@ class Solve {
     double *cpart = nullptr;  // moments-kernel reduction scratch
     unsigned *counter = nullptr;
     int64_t step = 0;      // steps taken (never beyond hd.nsteps)
+    int flip = 0;          // the current state is in buffer (step + flip) & 1 (two-step launches toggle it)
     int64_t rec_from = 0;  // drift records are valid from this step on
     int64_t red_to = 0;    // records of steps before this one have been added up
     std::vector<double2> cs_host;  // staging of uploads (kept until the next sync)
@@ -62,7 +63,11 @@ class Solve {
              hipStream_t st);
     void release();  // frees an owned workspace (the stream must be idle)
 
-    int cur() const { return (int)(step & 1); }
+    int cur() const { return (int)((step + flip) & 1); }
+    // Whether two steps may go in one launch: float64 (in float32 the one-step
+    // kernel, at two wavefronts per SIMD, is faster), full annulus, ntheta >
+    // 1, row blocks of at most FUSE_ROWS rows.
+    bool fusable() const;
     int waves() const { return L.nwaves; }
     bool rot() const { return p.sector != 8; }
     // Sets the step count on host and device (stream must be idle).

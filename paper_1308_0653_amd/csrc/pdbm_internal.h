@@ -16,6 +16,7 @@ constexpr int PART_RING = PDBM_MAX_CHUNK;  // records whose partial sums may wai
 constexpr int NXCD = 8;         // accelerator complex dies of an MI355X
 constexpr int NONEQ = PDBM_NONEQ_N;  // components of the non-equilibrium measures
 constexpr int STRIP = 64;       // theta columns stored per wavefront, one per lane
+constexpr int FUSE_ROWS = 16;   // most rows per wavefront of the two-step kernel (its edge cells sit in LDS)
 
 // Per-solve state in device memory written by the host.
 struct SolveState {
@@ -66,8 +67,16 @@ struct DiagCtl {
 // The step a solve takes is bases[solve] + step_off (bases NULL: step_off);
 // a solve whose step is at or beyond its nsteps is left alone.  A step that
 // makes a drift record leaves partial sums that launch_records adds up.
+// The state of step s lives in buffer (s + flip) & 1: packed launches pass
+// flip = 0, a single solve the parity its two-step launches have left.
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
-                       bool fp32, bool rot, hipStream_t st);
+                       int flip, bool fp32, bool rot, hipStream_t st);
+// Steps `step` and step + 1 of the single solve descs[0] in one pass: reads
+// buffer (step + flip) & 1 and writes the other one, so the caller toggles
+// flip.  Full annulus only (no rotated sector images), ntheta > 1, rows per
+// wavefront at most FUSE_ROWS, step + 2 <= nsteps.  Makes the drift records of
+// both steps as launch_step does.
+hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, bool fp32, hipStream_t st);
 // Non-equilibrium measures (Sec. II.E) of the state in buffer `cur` into
 // device memory out [NONEQ][nr][nt] float64.
 hipError_t launch_noneq(const SolveDesc &d, int cur, bool fp32, double *out, hipStream_t st);
@@ -86,6 +95,6 @@ int cell_blocks(int nr, int nt);
 // Wavefront tiles of a solve marched `rows` rows at a time.
 int solve_waves(int nr, int nt, int rows);
 // Rows per wavefront of the step kernel for a solve that has the GPU to itself.
-int rows_per_wave(int nr, int nt, bool fp32);
+int rows_per_wave(const pdbm_params &p);
 
 }  // namespace pdbm

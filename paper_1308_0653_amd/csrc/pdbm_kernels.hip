@@ -80,6 +80,7 @@ __device__ __forceinline__ void raw_moments(const real f[NQ], real &rho, real &j
 template <typename real>
 struct EqPoly {
     real c0, c1, c2, wx, wy;
+    EqPoly() = default;
     __device__ __forceinline__ EqPoly(real ux, real uy, real u2, real T)
     {
         const real iT = (real)1 / T;
@@ -225,6 +226,36 @@ __device__ __forceinline__ double from_left(double v)
 __device__ __forceinline__ double from_right(double v)
 {
     return __hiloint2double(dpp_shl1(__double2hiint(v)), dpp_shl1(__double2loint(v)));
+}
+
+// The same shifts with the value lane 0 (from_left_or) or lane 63
+// (from_right_or) receives from outside the wavefront given as `edge`
+// (bound_ctrl clear: a lane without a source lane keeps the old value).
+__device__ __forceinline__ int dpp_shr1_or(int edge, int v)
+{
+    return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_shl1_or(int edge, int v)
+{
+    return __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float from_left_or(float edge, float v)
+{
+    return __int_as_float(dpp_shr1_or(__float_as_int(edge), __float_as_int(v)));
+}
+__device__ __forceinline__ float from_right_or(float edge, float v)
+{
+    return __int_as_float(dpp_shl1_or(__float_as_int(edge), __float_as_int(v)));
+}
+__device__ __forceinline__ double from_left_or(double edge, double v)
+{
+    return __hiloint2double(dpp_shr1_or(__double2hiint(edge), __double2hiint(v)),
+                            dpp_shr1_or(__double2loint(edge), __double2loint(v)));
+}
+__device__ __forceinline__ double from_right_or(double edge, double v)
+{
+    return __hiloint2double(dpp_shl1_or(__double2hiint(edge), __double2hiint(v)),
+                            dpp_shl1_or(__double2loint(edge), __double2loint(v)));
 }
 
 // The step kernel reads the solve description through the constant address
@@ -804,7 +835,7 @@ __device__ __forceinline__ bool records(DescPtr dp, int64_t s)
 template <typename real, bool ROT>
 __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const SolveDesc *descs, const uint2 *tiles,
                                                                        int ntiles, const int64_t *bases,
-                                                                       int64_t step_off)
+                                                                       int64_t step_off, int flip)
 {
     const int nb = gridDim.x;
     const int blk = xcd_tile(blockIdx.x, nb);
@@ -822,7 +853,7 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
     const int64_t step = (bases ? bases[solve] : 0) + step_off;
     if (step >= dp->nsteps) return;
     const bool diag = records(dp, step);
-    const int cur = (int)(step & 1);
+    const int cur = (int)((step + flip) & 1);
     const StepBufs bufs{dp->f[cur], dp->f[cur ^ 1], dp->lam[cur], dp->lam[cur ^ 1]};
     __shared__ real prev[BLOCK / 64][NQ][64];
     double red[5] = {0, 0, 0, 0, 0};
@@ -845,6 +876,518 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
             const double v = wave_sum(red[i]);
+            if ((threadIdx.x & 63) == 0) part[i] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------ two steps per pass --
+// Steps s and s + 1 in one pass over f.  Stage A computes the state after
+// step s (g) one row ahead of stage B, which computes the state after step
+// s + 1 from g and stores it: g never leaves the wavefront.  Stage B's
+// azimuthal neighbours of lanes 0 and 63 are g at the columns bordering the
+// strip; the wavefront computes those cells itself at the start
+// (edge_cells), as the adjacent strips do in their own stage A.  A block of
+// R rows runs stage A on R + 2 rows and reads R + 4 rows of f, so each f
+// value is read about once and written once per two steps.
+
+// Per-cell quantities of one update (Sec. II.B-C): moments, F_k(T), the f^eq
+// polynomial and the BGK / chemical factors, evaluated as update_row does.
+template <typename real>
+struct Cell {
+    real rho, e, ux, uy, u2, T, beta, omega, keep, Bz;
+    double Td, a, b;
+    bool on;
+    real F[5];
+    EqPoly<real> EP;
+
+    __device__ __forceinline__ Cell(DescPtr dp, const real x[NQ], double lc)
+    {
+        real jx, jy;
+        raw_moments(x, rho, jx, jy, e);
+        const real irho = (real)1 / rho;
+        ux = jx * irho;
+        uy = jy * irho;
+        u2 = ux * ux + uy * uy;
+        T = e * irho - (real)0.5 * u2;
+        Td = (double)T;
+        weights(dp->A, Td, F);
+        EP = EqPoly<real>(ux, uy, u2, T);
+        a = 0.0;
+        b = 0.0;
+        double R = 0.0;
+        on = dp->reacts && Td > dp->T_th;
+        if (on) {
+            const double p = (double)rho * Td;
+            a = dp->w1 * ipow(p, dp->m);
+            b = dp->w2 * ipow(p, dp->n);
+            R = (1.0 - lc) * (a + b * lc);
+        }
+        beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
+        omega = (real)dp->omega;
+        keep = (real)1 - omega;
+        Bz = (real)-2 * beta * T;
+    }
+    // the rest particle after collision (it does not stream)
+    __device__ __forceinline__ real rest(real x0) const
+    {
+        return rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * x0;
+    }
+    // lambda after the closed-form Cochran step
+    __device__ __forceinline__ double reacted(DescPtr dp, double lc) const
+    {
+        if (on && a + b > 0.0) {
+            const double q1 = (1.0 - lc) * exp(-(a + b) * dp->dt);
+            return 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
+        }
+        return lc;
+    }
+};
+
+// Azimuthal neighbours of lanes 0 and 63 for stage A: the three gathered
+// loads of a row of the input state, written to an LDS row and read back by
+// every lane (hb[q] left halo of plane q, hb[33 + q] right halo; hl[0], hl[1]
+// lambda).
+template <typename real>
+struct LdsHalo {
+    const real *hb;
+    const double *hl;
+    __device__ __forceinline__ real left(int q) const { return hb[q]; }
+    __device__ __forceinline__ real right(int q) const { return hb[33 + q]; }
+    __device__ __forceinline__ double lleft() const { return hl[0]; }
+    __device__ __forceinline__ double lright() const { return hl[1]; }
+};
+// The gathered halo registers of one row (see Strip::load_halo).
+template <typename real>
+struct GatherHalo {
+    real h[2];
+    double hl;
+};
+
+// ... and from the edge cells of the intermediate state in LDS (stage B).  Of
+// each pair of opposite directions an edge cell keeps only the one lane 0
+// (left side) or lane 63 (right side) takes from that side, in slot
+// 4 (k - 1) + (direction mod 4).
+template <typename real>
+struct EdgeHalo {
+    const real *L, *R;
+    double ll, lr;
+    static __device__ __forceinline__ int slot(int q) { return ((q - 1) >> 3) * 4 + ((q - 1) & 3); }
+    __device__ __forceinline__ real left(int q) const { return L[slot(q)]; }
+    __device__ __forceinline__ real right(int q) const { return R[slot(q)]; }
+    __device__ __forceinline__ double lleft() const { return ll; }
+    __device__ __forceinline__ double lright() const { return lr; }
+};
+
+// One row of one of the two steps: the arithmetic of update_row, with the
+// azimuthal halo from H.  Radial neighbours: the row behind in compact LDS
+// slots (of each opposite pair of directions only the one that takes its
+// upwind value from behind, slot 4 (k - 1) + (direction mod 4); replaced by
+// this row's as they are read), the row ahead in `fn` (stage A) or in the
+// full LDS row `ga` (stage B).  STAGEA: the new row goes to `ga` and `lout`,
+// for every lane (stage B reads the periodic images too); otherwise it is
+// stored, for the strip's own columns.
+template <typename real, bool STAGEA, class Halo>
+__device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, real (*behind)[64], const real fc[NQ],
+                                          const real *fn, real (*ga)[64], const Halo &H, double lbehind, double lc,
+                                          double lahead, const bool mr[4], const bool mt[4], const real acr[4],
+                                          const real ctv[4], bool lr_behind, double csx, double csy, double &lout,
+                                          double red[5], bool diag)
+{
+    const DescPtr dp = S.dp;
+    const Cell<real> C(dp, fc, lc);
+    const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
+    const real kt = (real)(dp->dt_dth / ri);
+    real act[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) act[dd] = fabs(ctv[dd]) * kt;
+
+    const bool store = S.useful;
+    const int lane = S.lane;
+    const uint32_t rowoff = (uint32_t)ir * S.row_bytes;
+    const uint32_t pb = opaque(S.plane_bytes);
+
+    const real rest = C.rest(fc[0]);
+    if (STAGEA)
+        ga[0][lane] = rest;
+    else if (store)
+        bstore(rest, S.fout, S.vo, rowoff);
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real v = (real)speed(k);
+        const real rF = C.rho * C.F[k];
+        const real Ak = C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T);
+        const int base = 1 + 8 * (k - 1);
+        real o[8];
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            const real z = v * C.EP.w(dd);
+            real pp, pm;
+            C.EP.eval(z, pp, pm);
+            const real bz = C.Bz * z;
+            const int c = 4 * (k - 1) + dd;
+            const real back = behind[c][lane];
+            behind[c][lane] = mr[dd] ? fc[base + dd] : fc[base + dd + 4];
+#pragma unroll
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const int q = base + dd + 4 * sgn;
+                const real x = fc[q];
+                const real coll =
+                    sgn == 0 ? rF * pp * (Ak + bz) + C.omega * x : rF * pm * (Ak - bz) + C.omega * x;
+                const bool rb = sgn == 0 ? mr[dd] : !mr[dd];
+                real ahead;
+                if constexpr (STAGEA)
+                    ahead = fn[q];
+                else
+                    ahead = ga[q][lane];
+                const real nbr = rb ? back : ahead;
+                // every lane takes both shifts (lanes 0 and 63 the halo
+                // values), then selects
+                const real left = from_left_or(H.left(q), x);
+                const real right = from_right_or(H.right(q), x);
+                const bool tl = sgn == 0 ? mt[dd] : !mt[dd];
+                const real nbt = tl ? left : right;
+                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+            }
+        }
+        if (STAGEA) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) ga[base + i][lane] = o[i];
+        } else if (store) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bstore(o[i], S.fout, S.vo, rowoff + (uint32_t)(base + i) * pb);
+        }
+    }
+
+    const double uxd = (double)C.ux, uyd = (double)C.uy;
+    const double urp = uxd * csx + uyd * csy;
+    const double utp = -uxd * csy + uyd * csx;
+    const double lreac = C.reacted(dp, lc);
+    const double lleft = from_left_or(H.lleft(), lc);
+    const double lright = from_right_or(H.lright(), lc);
+    const double lr = (urp >= 0.0) == lr_behind ? lbehind : lahead;
+    const double lt = utp >= 0.0 ? lleft : lright;
+    const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
+    if (STAGEA)
+        lout = lnew;
+    else if (store)
+        bstore(lnew, S.lout, S.vol, (uint32_t)ir * S.lrow_bytes);
+
+    if (diag && store) diag_cell(red, (double)C.rho, uxd, uyd, C.Td, (double)C.e, lc, ri * dp->dr * dp->dth, dp->Q);
+}
+
+// The intermediate state at the columns bordering strip `strip`, c0 - 1
+// (left) and c0 + 64 (right) as periodic images, for the rows [i0, i1) of the
+// block: lane 32 side + e takes row i0 + e of its side.  Each lane gathers its
+// cell and the cell's upwind neighbours (radial ghost rules of Sec. II.D
+// included) and updates it as stage A of the strip owning the column does.
+// Of each opposite pair of directions it keeps the one that lane 0 (left
+// side) or lane 63 (right side) takes from there, and lambda.
+template <typename real>
+__device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int strip, int i0, int i1,
+                                           real (*ef)[FUSE_ROWS][16], double (*el)[FUSE_ROWS])
+{
+    const DescPtr dp = S.dp;
+    const int lane = S.lane, side = lane >> 5, e = lane & 31;
+    const int count = i1 - i0;
+    const int nr = dp->nr, nt = dp->nt;
+    const int r = i0 + min(e, count - 1);  // lanes past the block repeat its last row
+    const int c0 = strip * STRIP;
+    const int pc = side == 0 ? (c0 + nt - 1) % nt : (c0 + STRIP) % nt;
+    const int pl = (pc + nt - 1) % nt, pr = (pc + 1) % nt;
+    const int pk = (side == 0 ? c0 : c0 + STRIP - 1) % nt;  // column of lane 0 / lane 63
+    const double2 cs = dp->cs[pc], ck = dp->cs[pk];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    const real kcth = (real)ck.x, ksth = (real)ck.y;
+    const real kctv[4] = {-ksth, (real)SQH * (kcth - ksth), kcth, (real)SQH * (kcth + ksth)};
+
+    const uint32_t es = (uint32_t)sizeof(real), rowb = S.row_bytes, pb = S.plane_bytes, lrowb = S.lrow_bytes;
+    // radial neighbours: below row 0 the copy of row 0 (disc centre: with
+    // directions turned by 4), above row nr - 1 the copy of row nr - 1
+    const int rlo = max(r - 1, 0), rhi = min(r + 1, nr - 1);
+    const bool turn = r == 0 && dp->disc;
+    real x[NQ], nbr[NQ], nbt[NQ];
+    const uint32_t oc = (uint32_t)r * rowb + (uint32_t)pc * es;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) bload(x[q], S.fin, oc + (uint32_t)q * pb, 0u);
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8, dd = dir & 3, sgn = dir >> 2;
+        const bool mr = crv[dd] >= (real)0, mt = ctv[dd] >= (real)0;
+        const bool lower = sgn == 0 ? mr : !mr;
+        const int plane = lower && turn ? base + ((dir + 4) & 7) : q;
+        bload(nbr[q], S.fin, (uint32_t)(lower ? rlo : rhi) * rowb + (uint32_t)plane * pb + (uint32_t)pc * es, 0u);
+        const bool tl = sgn == 0 ? mt : !mt;
+        bload(nbt[q], S.fin, (uint32_t)r * rowb + (uint32_t)q * pb + (uint32_t)(tl ? pl : pr) * es, 0u);
+    }
+    double lc, lb, la, lL, lR;
+    bload(lc, S.lin, (uint32_t)r * lrowb + (uint32_t)pc * 8u, 0u);
+    bload(lb, S.lin, (uint32_t)rlo * lrowb + (uint32_t)pc * 8u, 0u);
+    bload(la, S.lin, (uint32_t)rhi * lrowb + (uint32_t)pc * 8u, 0u);
+    bload(lL, S.lin, (uint32_t)r * lrowb + (uint32_t)pl * 8u, 0u);
+    bload(lR, S.lin, (uint32_t)r * lrowb + (uint32_t)pr * 8u, 0u);
+
+    const Cell<real> C(dp, x, lc);
+    const double ri = dp->r_min + ((double)r + 0.5) * dp->dr;
+    const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
+    real g[NQ];
+    g[0] = C.rest(x[0]);
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real v = (real)speed(k);
+        const real rF = C.rho * C.F[k];
+        const real Ak = C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T);
+        const int base = 1 + 8 * (k - 1);
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            const real z = v * C.EP.w(dd);
+            real pp, pm;
+            C.EP.eval(z, pp, pm);
+            const real bz = C.Bz * z;
+            const real acr = fabs(crv[dd]) * kr, act = fabs(ctv[dd]) * kt;
+#pragma unroll
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const int q = base + dd + 4 * sgn;
+                const real xq = x[q];
+                const real coll =
+                    sgn == 0 ? rF * pp * (Ak + bz) + C.omega * xq : rF * pm * (Ak - bz) + C.omega * xq;
+                g[q] = coll - v * (acr * (xq - nbr[q]) + act * (xq - nbt[q]));
+            }
+        }
+    }
+    const double uxd = (double)C.ux, uyd = (double)C.uy;
+    const double urp = uxd * cs.x + uyd * cs.y;
+    const double utp = -uxd * cs.y + uyd * cs.x;
+    const double lr = urp >= 0.0 ? lb : la;
+    const double lt = utp >= 0.0 ? lL : lR;
+    const double lnew =
+        C.reacted(dp, lc) - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
+    if (e < count) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd) {
+                const bool first = (kctv[dd] >= (real)0) != (side == 1);  // keep direction dd, else dd + 4
+                const int q = 1 + 8 * k + dd;
+                ef[side][e][4 * k + dd] = first ? g[q] : g[q + 4];
+            }
+        el[side][e] = lnew;
+    }
+}
+
+// Orders this wavefront's LDS writes before its reads of what other lanes
+// wrote (a wavefront's LDS operations complete in order; this keeps the
+// compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Plane q of the ghost row beyond the grid made from row `src`: the copy of
+// the boundary row, with directions turned by 4 below the disc centre.
+__device__ __forceinline__ int ghost_plane(int q, bool turn)
+{
+    if (q == 0 || !turn) return q;
+    const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8;
+    return base + ((dir + 4) & 7);
+}
+
+// Fills the compact slots of the row behind (see stage_row) from a full row.
+template <typename real>
+__device__ __forceinline__ void fill_behind(real (*behind)[64], const real x[NQ], const bool mr[4], int lane)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) behind[4 * k + dd][lane] = mr[dd] ? x[1 + 8 * k + dd] : x[5 + 8 * k + dd];
+}
+
+// Work of one wavefront of the two-step kernel: strip `strip`, rows [i0, i1)
+// (at most FUSE_ROWS), marched outward or, with `down`, inward.  Positions p
+// count rows in marching order from the first row of the block (p = 0);
+// stage A runs on positions -1 .. R where they are grid rows, stage B on
+// 0 .. R - 1, one position behind stage A.  LDS per wavefront: the compact
+// rows behind of f (fb) and of g (gb), the full row of g just computed (ga)
+// and the edge cells.
+template <typename real>
+__device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
+                                       real (*fb)[64], real (*gb)[64], real (*ga)[64], real (*ef)[FUSE_ROWS][16],
+                                       double (*el)[FUSE_ROWS], real *hb, double *hbl, double redA[5],
+                                       double redB[5], bool diagA, bool diagB)
+{
+    const Strip<real, false> S(dp, bufs, strip);
+    edge_cells<real>(S, strip, i0, i1, ef, el);
+    wave_lds_sync();
+
+    const int lane = S.lane;
+    const double2 cs = dp->cs[S.pc];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    const real kr = (real)dp->dt_dr;
+    real acr[4];
+    bool mr[4], mt[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        acr[dd] = fabs(crv[dd]) * kr;
+        mr[dd] = (crv[dd] >= (real)0) != down;
+        mt[dd] = ctv[dd] >= (real)0;
+    }
+    const int nr = dp->nr;
+    const int step = down ? -1 : 1;
+    const int first = down ? i1 - 1 : i0;
+    const int count = i1 - i0;
+    const int rbefore = first - step, rafter = first + count * step;  // rows of positions -1 and R
+    const bool vlo = rbefore >= 0 && rbefore < nr, vhi = rafter >= 0 && rafter < nr;
+    const bool turn_lo = rbefore < 0 && dp->disc, turn_hi = rafter < 0 && dp->disc;
+
+    // f at positions p (fc) and p + 1 (fn) in registers; f(p + 2) is loaded
+    // into fc once stage A has used it, and the two swap at the end of the
+    // pass (the loop is not unrolled: one pass is already half the
+    // instruction cache)
+    real fc[NQ], fn[NQ];
+    double lp, lc, ln, lx = 0.0;             // lambda of f at positions p-1, p, p+1, p+2
+    double glp = 0.0, glc = 0.0, gln = 0.0;  // lambda of g at positions p-2, p-1, p
+    GatherHalo<real> hc, hn, hx;
+    int p0;
+    {
+        real t[NQ];
+        if (vlo) {
+            // stage A starts at position -1: behind it position -2 (a ghost
+            // beyond the grid), centre -1, ahead 0
+            S.load_row(rbefore, fc, lc);
+            S.load_halo(rbefore, hc.h, hc.hl);
+            S.load_row(first, fn, ln);
+            S.load_halo(first, hn.h, hn.hl);
+            row_or_ghost(S, rbefore - step, t, lp, fc, lc);
+            p0 = -1;
+        } else {
+            S.load_row(first, fc, lc);
+            S.load_halo(first, hc.h, hc.hl);
+            row_or_ghost(S, first + step, fn, ln, fc, lc);
+            if (count > 1 || vhi) S.load_halo(first + step, hn.h, hn.hl);
+            row_or_ghost(S, rbefore, t, lp, fc, lc);
+            p0 = 0;
+        }
+        fill_behind(fb, t, mr, lane);
+    }
+
+    for (int p = p0; p <= count; ++p) {
+        const int ir = first + p * step;
+        // g(p - 1), centre of stage B, before stage A replaces it in ga
+        real gc[NQ];
+        if (p >= 1) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) gc[q] = ga[q][lane];
+        } else if (p == 0 && vlo) {
+            // g(-1), computed by stage A at position -1, is the row behind
+            // stage B's first row
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd)
+                    gb[4 * k + dd][lane] = mr[dd] ? ga[1 + 8 * k + dd][lane] : ga[5 + 8 * k + dd][lane];
+        }
+        // (A) first step at position p, or the ghost beyond the grid
+        if (p < count || vhi) {
+            // the row's gathered halo values into LDS, read back by every lane
+            hb[lane] = hc.h[0];
+            if (lane < 2) {
+                hb[64 + lane] = hc.h[1];
+                hbl[lane] = hc.hl;
+            }
+            wave_lds_sync();
+            const LdsHalo<real> H{hb, hbl};
+            stage_row<real, true>(S, ir, fb, fc, fn, ga, H, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, gln,
+                                  redA, diagA && p >= 0 && p < count);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) ga[q][lane] = turn_hi ? gc[ghost_plane(q, true)] : gc[q];
+            gln = glc;
+        }
+        // f at position p + 2 (the row ahead of the next stage A) replaces f(p)
+        if (p + 1 < count || (p + 1 == count && vhi)) row_or_ghost(S, ir + 2 * step, fc, lx, fn, ln);
+        if (p + 2 < count || (p + 2 == count && vhi)) S.load_halo(ir + 2 * step, hx.h, hx.hl);
+        // (B) second step at position p - 1
+        if (p == 0 && !vlo) {
+            // the row behind stage B's first row is the ghost of g(0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd) {
+                    const real a = ga[ghost_plane(1 + 8 * k + dd, turn_lo)][lane];
+                    const real b = ga[ghost_plane(5 + 8 * k + dd, turn_lo)][lane];
+                    gb[4 * k + dd][lane] = mr[dd] ? a : b;
+                }
+            glc = gln;
+        } else if (p > 0) {
+            const int e = ir - step - i0;
+            const EdgeHalo<real> H{ef[0][e], ef[1][e], el[0][e], el[1][e]};
+            double unused;
+            stage_row<real, false>(S, ir - step, gb, gc, nullptr, ga, H, glp, glc, gln, mr, mt, acr, ctv, !down,
+                                   cs.x, cs.y, unused, redB, diagB);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const real t = fc[q];
+            fc[q] = fn[q];
+            fn[q] = t;
+        }
+        hc = hn;
+        hn = hx;
+        lp = lc;
+        lc = ln;
+        ln = lx;
+        glp = glc;
+        glc = gln;
+        // Compiler-only barrier: the LDS rows must not be promoted to
+        // registers across passes.
+        asm volatile("" ::: "memory");
+    }
+}
+
+// Steps `step` and step + 1 of one solve (descs[0]); tiles as k_step's.  One
+// wavefront per SIMD in both precisions (the two steps' rows fill the
+// register file and the LDS rows of four wavefronts most of a CU's LDS).
+template <typename real>
+__global__ __launch_bounds__(BLOCK, 1) void k_step2(const SolveDesc *descs, int ntiles,
+                                                                       int64_t step, int flip)
+{
+    const int nb = gridDim.x;
+    const int blk = xcd_tile(blockIdx.x, nb);
+    const int t = __builtin_amdgcn_readfirstlane(blk * (BLOCK / 64) + (threadIdx.x >> 6));
+    if (t >= ntiles) return;
+    const DescPtr dp = (DescPtr)descs;
+    const bool diagA = records(dp, step), diagB = records(dp, step + 1);
+    const int cur = (int)((step + flip) & 1);
+    const StepBufs bufs{dp->f[cur], dp->f[cur ^ 1], dp->lam[cur], dp->lam[cur ^ 1]};
+    __shared__ real fb[BLOCK / 64][16][64];
+    __shared__ real gb[BLOCK / 64][16][64];
+    __shared__ real ga[BLOCK / 64][NQ][64];
+    __shared__ real ef[BLOCK / 64][2][FUSE_ROWS][16];
+    __shared__ double el[BLOCK / 64][2][FUSE_ROWS];
+    __shared__ real hb[BLOCK / 64][66];
+    __shared__ double hbl[BLOCK / 64][2];
+    const int w = threadIdx.x >> 6;
+    double redA[5] = {0, 0, 0, 0, 0}, redB[5] = {0, 0, 0, 0, 0};
+    const int rows = dp->rows, nstrip = dp->nstrip;
+    const int rb = t / nstrip, strip = t - rb * nstrip;
+    const int i0 = rb * rows;
+    const int i1 = min(i0 + rows, dp->nr);
+    march2<real>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], redA,
+                 redB, diagA, diagB);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        if (!(s == 0 ? diagA : diagB)) continue;
+        const int64_t slot = ((step + s) / dp->diag_every) % PART_RING;
+        double *part = dp->wpart + ((size_t)slot * dp->nwaves + t) * 5;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double v = wave_sum(s == 0 ? redA[i] : redB[i]);
             if ((threadIdx.x & 63) == 0) part[i] = v;
         }
     }
@@ -1065,25 +1608,36 @@ int solve_waves(int nr, int nt, int rows)
 }
 
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
-                       bool fp32, bool rot, hipStream_t st)
+                       int flip, bool fp32, bool rot, hipStream_t st)
 {
     const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0) return hipSuccess;
     if (fp32) {
         if (rot)
             hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off);
+                               step_off, flip);
         else
             hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off);
+                               step_off, flip);
     } else {
         if (rot)
             hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off);
+                               step_off, flip);
         else
             hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off);
+                               step_off, flip);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, bool fp32, hipStream_t st)
+{
+    const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
+    if (nb == 0) return hipSuccess;
+    if (fp32)
+        hipLaunchKernelGGL(k_step2<float>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
+    else
+        hipLaunchKernelGGL(k_step2<double>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
     return hipGetLastError();
 }
 

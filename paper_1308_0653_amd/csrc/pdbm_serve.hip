@@ -158,7 +158,8 @@ class Pack {
     {
         const int nm = (int)members.size();
         hipError_t e = hipSuccess;
-        for (int i = 0; i < n && e == hipSuccess; ++i) e = launch_step(ddescs, dtiles, ntiles, dbases, i, fp32, rot, st);
+        for (int i = 0; i < n && e == hipSuccess; ++i)
+            e = launch_step(ddescs, dtiles, ntiles, dbases, i, 0, fp32, rot, st);
         if (e == hipSuccess) e = launch_records(ddescs, nm, dbases, 0, n, st);
         if (e == hipSuccess) e = launch_advance(dbases, nm, n, st);
         return e;

@@ -55,7 +55,7 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
         subprocess.run(cmd, cwd=tmp, check=True, capture_output=True)
         asm = open(out).read()
     bodies = list(_kernel_bodies(asm, "k_step"))
-    assert len(bodies) == 4
+    assert len(bodies) == 6  # k_step: 2 precisions x (full annulus, rotated sector); k_step2: 2 precisions
     sreg = r"s\[\d+:\d+\]"
     for name, lines in bodies:
         # An exec-narrowing region opens with s_and_saveexec_b64 sX (on every
@@ -89,9 +89,10 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
 
 
 def test_step_kernel_uses_no_scratch_memory():
-    """Register spills of the step kernel must stay in registers (AGPRs): a
+    """Register spills of the step kernels must stay in registers (AGPRs): a
     spill to scratch memory inside the row loop adds memory round trips to
-    every row.  Checked on the code-object metadata of every variant."""
+    every row.  Checked on the code-object metadata of every variant of the
+    one-step and the two-step kernel."""
     src = os.path.join(B.CSRC, "pdbm_kernels.hip")
     with tempfile.TemporaryDirectory() as tmp:
         out = os.path.join(tmp, "k.s")
@@ -106,4 +107,4 @@ def test_step_kernel_uses_no_scratch_memory():
             continue
         seen += 1
         assert int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1)) == 0, name
-    assert seen == 4
+    assert seen == 6

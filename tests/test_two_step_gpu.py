@@ -1,0 +1,103 @@
+"""Two steps per launch against one step per launch.
+
+Solver.step(n) advances a full-annulus solve with ntheta > 1 in pairs of
+steps, each pair in one pass over f (k_step2); step(1) always takes the
+one-step kernel.  Both do the same arithmetic per cell in the same order, so
+their states agree to rounding.  The cases cover strip and row-block edges
+(blocks of one row up to the 16-row limit, marched both ways), the disc
+centre, both precisions, odd step counts (pairs and one single step), the
+drift records of both steps of a pair, and checkpoints taken after an odd
+number of pairs, when the state sits in the buffer of the other parity.
+Parity of the paired path with the oracle is covered by the parity and
+strip-edge tests, which step in pairs.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from paper_1308_0653_amd import pdbm as P
+from paper_1308_0653_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(nr, nt, r_min=0.3, seed=0):
+    # a reacting, moving, noisy state: ignition inside r < 0.55; dt keeps
+    # the radial Courant number of the fastest speed (12.5) at about 0.35
+    dt = min(2e-5, 0.35 * (1.0 - r_min) / nr / 12.5)
+    return replace(W.small_fp64(), nr=nr, ntheta=nt, r_min=r_min, r_max=1.0, dt=dt, tau=2.5 * dt, r_split=0.55,
+                   p_noise=1e-3, seed=seed)
+
+
+def _solver(w, precision, diag_every=0):
+    return P.Solver(P.make_params(**w.params_kw(), precision=precision, diag_every=diag_every),
+                    P.make_ic(**w.ic_kw()))
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# float64 agrees to a few units in the last place; float32 state values are
+# compared relative to their own scale
+TOL = {P.PDBM_FP64: 1e-13, P.PDBM_FP32: 1e-6}
+
+
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+@pytest.mark.parametrize("nr,nt,r_min", [(1, 64, 0.3), (2, 65, 0.3), (5, 2, 0.3), (33, 65, 0.3), (17, 200, 0.0),
+                                         (40, 130, 0.0), (64, 64, 0.3), (8192, 130, 0.3)])
+def test_pairs_match_single_steps(precision, nr, nt, r_min):
+    w = _case(nr, nt, r_min)
+    n = 7  # three pairs and one single step
+    a = _solver(w, precision)
+    a.step(n)
+    b = _solver(w, precision)
+    for _ in range(n):
+        b.step(1)
+    assert a.step_count == b.step_count == n
+    fa, la = a.read_f()
+    fb, lb = b.read_f()
+    ef, el = _rel(fa, fb), _rel(la, lb)
+    print(f"nr={nr} nt={nt} r_min={r_min} prec={precision}: f {ef:.2e} lambda {el:.2e}", flush=True)
+    assert ef <= TOL[precision] and el <= TOL[precision]
+    Fa, _ = a.moments()
+    Fb, _ = b.moments()
+    assert np.abs(Fa - Fb).max() <= TOL[precision] * max(np.abs(Fb).max(), 1.0)
+
+
+def test_pair_drift_records_match_single_steps():
+    w = _case(33, 130)
+    a = _solver(w, P.PDBM_FP64, diag_every=1)
+    a.step(130)  # more records than the partial-sum ring holds
+    b = _solver(w, P.PDBM_FP64, diag_every=1)
+    for _ in range(130):
+        b.step(1)
+    ha, hb = a.diag_history(), b.diag_history()
+    assert len(ha) == len(hb) == 130
+    for ra, rb in zip(ha, hb):
+        assert ra["step"] == rb["step"]
+        assert ra["n_nonfinite"] == rb["n_nonfinite"] == 0 and ra["n_nonphys"] == rb["n_nonphys"] == 0
+        for k in ("mass", "energy", "chem"):
+            assert abs(ra[k] - rb[k]) <= 1e-13 * abs(rb[k]), (ra, rb)
+
+
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_checkpoint_after_odd_number_of_pairs(precision):
+    w = _case(20, 70, r_min=0.0)
+    ref = _solver(w, precision)
+    ref.step(10)
+    a = _solver(w, precision)
+    a.step(6)  # three pairs: the state sits in the buffer of the other parity
+    blob = a.get_state()
+    b = _solver(w, precision)
+    b.set_state(blob)
+    assert b.step_count == 6
+    for s in (a, b):
+        s.step(4)
+    fr, lr = ref.read_f()
+    for s in (a, b):
+        f, lam = s.read_f()
+        assert np.array_equal(f, fr) and np.array_equal(lam, lr)
+    # the non-equilibrium measures read the current buffer too
+    assert np.array_equal(a.noneq(), ref.noneq())
