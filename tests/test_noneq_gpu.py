@@ -114,7 +114,8 @@ def test_noneq_batch_member_and_async_match_solo():
     b.step(25)
     for i, w in enumerate(ws):
         solo = P.Solver(_params(w), P.make_ic(**w.ic_kw()))
-        solo.step(25)
+        for _ in range(25):  # one step per launch, as the packed members
+            solo.step(1)
         D = solo.noneq()
         assert np.array_equal(b.noneq(i), D)
         t = torch.empty((P.PDBM_NONEQ_N, w.nr, w.ntheta), dtype=torch.float64, device="cuda")
