@@ -27,7 +27,10 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Padded row length: a multiple of the 64 columns of one wavefront, so that
 // every wavefront's store of one velocity plane covers whole cache lines.
-int pitch_of(int nt) { return nt <= 16 ? nt : (nt + STRIP - 1) / STRIP * STRIP; }
+// Rows are padded to whole 64-column strips (a strip's loads and stores
+// then cover whole cache lines); a single column gets a pitch of 2, so that
+// the pairs of the f layout stay 16-byte aligned.
+int pitch_of(int nt) { return nt == 1 ? 2 : (nt + STRIP - 1) / STRIP * STRIP; }
 
 bool is_fin(double x) { return std::isfinite(x); }
 
@@ -526,31 +529,35 @@ int pdbm_diag_history(pdbm_solver *h, pdbm_diag *out, int32_t cap, int32_t *n)
 
 }  // extern "C"
 
-// f on the device is [nr][NQ][pitch]; host arrays are [NQ][nr][ntheta].
+// f on the device: r rows of 33 * pitch elements in the paired layout of
+// elem_of; host arrays are [NQ][nr][ntheta].  Whole buffers are copied and
+// rearranged on the host.
 static hipError_t f_to_host(const Solve &s, void *host)
 {
     const int nr = s.p.nr, nt = s.p.ntheta;
-    const size_t esz = s.L.esz, pitch = s.L.pitch;
-    for (int q = 0; q < NQ; ++q) {
-        hipError_t e = hipMemcpy2D((char *)host + (size_t)q * nr * nt * esz, nt * esz,
-                                   (const char *)s.hd.f[s.cur()] + q * pitch * esz, NQ * pitch * esz, nt * esz, nr,
-                                   hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return e;
-    }
+    const size_t esz = s.L.esz, pitch = s.L.pitch, rstride = (size_t)NQ * pitch;
+    std::vector<char> raw((size_t)nr * rstride * esz);
+    hipError_t e = hipMemcpy(raw.data(), s.hd.f[s.cur()], raw.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    for (int q = 0; q < NQ; ++q)
+        for (int ir = 0; ir < nr; ++ir)
+            for (int jt = 0; jt < nt; ++jt)
+                std::memcpy((char *)host + (((size_t)q * nr + ir) * nt + jt) * esz,
+                            raw.data() + (ir * rstride + elem_of(q, jt, pitch)) * esz, esz);
     return hipSuccess;
 }
 
 static hipError_t f_to_device(const Solve &s, int buf, const void *host)
 {
     const int nr = s.p.nr, nt = s.p.ntheta;
-    const size_t esz = s.L.esz, pitch = s.L.pitch;
-    for (int q = 0; q < NQ; ++q) {
-        hipError_t e = hipMemcpy2D((char *)s.hd.f[buf] + q * pitch * esz, NQ * pitch * esz,
-                                   (const char *)host + (size_t)q * nr * nt * esz, nt * esz, nt * esz, nr,
-                                   hipMemcpyHostToDevice);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const size_t esz = s.L.esz, pitch = s.L.pitch, rstride = (size_t)NQ * pitch;
+    std::vector<char> raw((size_t)nr * rstride * esz, 0);
+    for (int q = 0; q < NQ; ++q)
+        for (int ir = 0; ir < nr; ++ir)
+            for (int jt = 0; jt < nt; ++jt)
+                std::memcpy(raw.data() + (ir * rstride + elem_of(q, jt, pitch)) * esz,
+                            (const char *)host + (((size_t)q * nr + ir) * nt + jt) * esz, esz);
+    return hipMemcpy(s.hd.f[buf], raw.data(), raw.size(), hipMemcpyHostToDevice);
 }
 
 extern "C" {

@@ -18,6 +18,19 @@ constexpr int NONEQ = PDBM_NONEQ_N;  // components of the non-equilibrium measur
 constexpr int STRIP = 64;       // theta columns stored per wavefront, one per lane
 constexpr int FUSE_ROWS = 16;   // most rows per wavefront of the two-step kernel (its edge cells sit in LDS)
 
+// Layout of f within one r row (33 * pitch elements): the rest particle's
+// plane [pitch], then the 16 pairs of opposite directions of each speed, pair
+// c = 4 (k - 1) + (i mod 4) holding directions i and i + 4 interleaved per
+// column ([pitch][2]).  The pair of a cell is one 16-byte (float64) or
+// 8-byte (float32) access, and the two members are updated together.
+__host__ __device__ constexpr int pair_of(int q) { return 4 * ((q - 1) / 8) + ((q - 1) & 3); }
+__host__ __device__ constexpr int member_of(int q) { return ((q - 1) & 7) >> 2; }
+// Element offset of velocity q, column col, from the start of its r row.
+__host__ __device__ constexpr int64_t elem_of(int q, int64_t col, int64_t pitch)
+{
+    return q == 0 ? col : pitch + 2 * pitch * pair_of(q) + 2 * col + member_of(q);
+}
+
 // Per-solve state in device memory written by the host.
 struct SolveState {
     int64_t rec_from;  // drift records are produced for steps >= rec_from only
@@ -27,7 +40,7 @@ struct SolveState {
 // it from device memory (one entry, or a table of entries for a packed
 // launch over many solves); the cell kernels take it by value.
 struct SolveDesc {
-    void *f[2];         // [nr][NQ][pitch] float or double: the 33 velocity rows of one r row are adjacent
+    void *f[2];         // float or double, r rows of NQ * pitch elements in the layout of elem_of
     double *lam[2];     // [nr][pitch]
     const double2 *cs;  // [ntheta] (cos theta_j, sin theta_j)
     SolveState *state;
@@ -36,7 +49,7 @@ struct SolveDesc {
     int32_t nr, nt, pitch, sector;
     int32_t m, n, disc, reacts;          // disc: r_min == 0; reacts: w1+w2 > 0
     int32_t rows, nwaves, nstrip, diag_every;  // rows marched by one wavefront; its wavefronts
-    int64_t plane;    // elements between the rows of consecutive velocities (= pitch)
+    int64_t plane;    // elements of the rest particle's plane (= pitch; a pair takes 2 * plane)
     int64_t rstride;  // elements between consecutive r rows of f (= NQ * pitch)
     int64_t nsteps;   // the solve stops advancing once it has taken this many steps
     double r_min, dr, dth;

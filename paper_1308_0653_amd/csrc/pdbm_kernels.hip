@@ -310,6 +310,38 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint3
     t.y = __double2hiint(v);
     __builtin_amdgcn_raw_buffer_store_b64(t, r, vo, so, STORE_NT);
 }
+// Both members of a pair of opposite directions (see elem_of): one 8-byte
+// (float32) or 16-byte (float64) access per lane.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void bload2(float &a, float &b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    const i32x2 t = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    a = __int_as_float(t.x);
+    b = __int_as_float(t.y);
+}
+__device__ __forceinline__ void bload2(double &a, double &b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    const i32x4 t = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+    a = __hiloint2double(t.y, t.x);
+    b = __hiloint2double(t.w, t.z);
+}
+__device__ __forceinline__ void bstore2(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    i32x2 t;
+    t.x = __float_as_int(a);
+    t.y = __float_as_int(b);
+    __builtin_amdgcn_raw_buffer_store_b64(t, r, vo, so, STORE_NT);
+}
+__device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    i32x4 t;
+    t.x = __double2loint(a);
+    t.y = __double2hiint(a);
+    t.z = __double2loint(b);
+    t.w = __double2hiint(b);
+    __builtin_amdgcn_raw_buffer_store_b128(t, r, vo, so, STORE_NT);
+}
+
 // Keeps a scalar offset opaque to the optimiser, so that the 33 plane offsets
 // are re-derived by one scalar add each instead of being hoisted out of the
 // row loop (where they would not fit in scalar registers).
@@ -335,9 +367,11 @@ template <typename real, bool ROT>
 struct Strip {
     DescPtr dp;
     __amdgpu_buffer_rsrc_t fin, fout, lin, lout;
-    uint32_t vo, vol;     // byte offsets of this lane's column in f and lambda rows
+    uint32_t vo, vo2, vol;   // byte offsets of this lane's column: rest plane, pair, lambda
     uint32_t vh1, vh2, vhl;  // byte offsets of this lane's halo gathers (plane and column)
-    uint32_t row_bytes, lrow_bytes, plane_bytes;
+    uint32_t row_bytes, lrow_bytes, rest_bytes, pair_bytes;
+    uint32_t poff[4];     // rotated sectors: byte offset of the pair holding this lane's directions dd, dd + 4
+    bool pswap[4];        // ... and whether its members come in the other order
     int lane, pc, rot;    // physical column, direction shift of this lane's data
     bool useful;
 
@@ -363,10 +397,18 @@ struct Strip {
         rot = ROT ? ((-wraps * sec) & 7) : 0;
         useful = col < nt;
         vo = (uint32_t)pc * (uint32_t)sizeof(real);
+        vo2 = 2u * vo;
         vol = (uint32_t)pc * 8u;
         row_bytes = (uint32_t)dp->rstride * (uint32_t)sizeof(real);
         lrow_bytes = (uint32_t)dp->pitch * 8u;
-        plane_bytes = (uint32_t)dp->plane * (uint32_t)sizeof(real);
+        rest_bytes = (uint32_t)dp->plane * (uint32_t)sizeof(real);
+        pair_bytes = 2u * rest_bytes;
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            // direction dd of this lane's data is direction (dd + rot) % 8
+            poff[dd] = vo2 + rest_bytes + (uint32_t)((dd + rot) & 3) * pair_bytes;
+            pswap[dd] = ((dd + rot) & 4) != 0;
+        }
         // halo columns: c0 - 1 (0 <= c0 < nt) and c0 + 64, as periodic images
         const int cl = c0 == 0 ? nt - 1 : c0 - 1;
         const int rl = ROT && c0 == 0 ? (sec & 7) : 0;
@@ -378,26 +420,36 @@ struct Strip {
         // 32; lambda gather: lane 0 left, lane 1 right (other lanes repeat a
         // valid address)
         const int es = (int)sizeof(real);
-        vh1 = lane <= 32 ? (uint32_t)(plane_of(lane, rl) * dp->plane + cl) * es
-                         : (uint32_t)(plane_of(lane - 33, rr) * dp->plane + cr) * es;
-        vh2 = lane < 2 ? (uint32_t)(plane_of(31 + lane, rr) * dp->plane + cr) * es : (uint32_t)cl * es;
+        const int64_t pt = dp->pitch;
+        vh1 = lane <= 32 ? (uint32_t)elem_of(plane_of(lane, rl), cl, pt) * es
+                         : (uint32_t)elem_of(plane_of(lane - 33, rr), cr, pt) * es;
+        vh2 = lane < 2 ? (uint32_t)elem_of(plane_of(31 + lane, rr), cr, pt) * es : (uint32_t)cl * es;
         vhl = lane == 1 ? (uint32_t)cr * 8u : (uint32_t)cl * 8u;
     }
 
     __device__ __forceinline__ void load_row(int row, real f[NQ], double &lam) const
     {
         uint32_t so = (uint32_t)row * row_bytes;
+        bload(f[0], fin, vo, so);
         if (ROT) {
-            // this lane's data of direction dir lives in plane (dir + rot) % 8
-            bload(f[0], fin, vo, so);
+            // this lane's data of direction dir lives in direction (dir + rot) % 8
 #pragma unroll
-            for (int q = 1; q < NQ; ++q) bload(f[q], fin, vo + (uint32_t)plane_of(q, rot) * plane_bytes, so);
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t sk = so + (uint32_t)k * 4u * pair_bytes;
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd) {
+                    real a, b;
+                    bload2(a, b, fin, poff[dd], sk);
+                    f[1 + 8 * k + dd] = pswap[dd] ? b : a;
+                    f[5 + 8 * k + dd] = pswap[dd] ? a : b;
+                }
+            }
         } else {
-            bload(f[0], fin, vo, so);
+            so = opaque(so + rest_bytes);
 #pragma unroll
-            for (int q = 1; q < NQ; ++q) {
-                so = opaque(so + plane_bytes);
-                bload(f[q], fin, vo, so);
+            for (int c = 0; c < 16; ++c) {
+                bload2(f[1 + 8 * (c >> 2) + (c & 3)], f[5 + 8 * (c >> 2) + (c & 3)], fin, vo2, so);
+                so = opaque(so + pair_bytes);
             }
         }
         bload(lam, lin, vol, (uint32_t)row * lrow_bytes);
@@ -488,10 +540,11 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
 
     const bool store = S.useful;
     const int lane = S.lane;
-    // output plane q of this row sits at rowoff + q * pb (pb re-derived per
-    // row so the 33 products stay scalar arithmetic inside the loop)
+    // pair c of this row sits at rowoff + rest plane + c * pb (pb re-derived
+    // per row so the 16 products stay scalar arithmetic inside the loop)
     const uint32_t rowoff = (uint32_t)ir * S.row_bytes;
-    const uint32_t pb = opaque(S.plane_bytes);
+    const uint32_t pb = opaque(S.pair_bytes);
+    const uint32_t pairs = rowoff + S.rest_bytes;
 
     // rest particle: no streaming
     const real rest = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * fc[0];
@@ -538,10 +591,8 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
             // stored lanes are never rotated sector images
             if (dd % G == G - 1 && store) {
 #pragma unroll
-                for (int e = dd + 1 - G; e <= dd; ++e) {
-                    bstore(o[e], S.fout, S.vo, rowoff + (uint32_t)(base + e) * pb);
-                    bstore(o[e + 4], S.fout, S.vo, rowoff + (uint32_t)(base + e + 4) * pb);
-                }
+                for (int e = dd + 1 - G; e <= dd; ++e)
+                    bstore2(o[e], o[e + 4], S.fout, S.vo2, pairs + (uint32_t)(4 * (k - 1) + e) * pb);
             }
         }
     }
@@ -682,15 +733,19 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
     const bool store = row < nr;
     const __amdgpu_buffer_rsrc_t fin = rsrc_of(bufs.f_in), fout = rsrc_of(bufs.f_out);
     const __amdgpu_buffer_rsrc_t lin = rsrc_of(bufs.lam_in), lout = rsrc_of(bufs.lam_out);
-    const uint32_t rowb = (uint32_t)dp->rstride * (uint32_t)sizeof(real);
-    const uint32_t pb = (uint32_t)dp->plane * (uint32_t)sizeof(real);
+    const uint32_t es = (uint32_t)sizeof(real);
+    const uint32_t rowb = (uint32_t)dp->rstride * es;
+    const uint32_t rb = (uint32_t)dp->plane * es, pb = 2u * rb;  // rest plane, one pair (column 0)
+    const int64_t pt = dp->pitch;
     const uint32_t lrowb = (uint32_t)dp->pitch * 8u;
     const uint32_t vo = (uint32_t)re * rowb, vol = (uint32_t)re * lrowb;
 
     real fc[NQ];
     double lc;
+    bload(fc[0], fin, vo, 0u);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) bload(fc[q], fin, vo, (uint32_t)q * pb);
+    for (int c = 0; c < 16; ++c)
+        bload2(fc[1 + 8 * (c >> 2) + (c & 3)], fc[5 + 8 * (c >> 2) + (c & 3)], fin, vo, rb + (uint32_t)c * pb);
     bload(lc, lin, vol, 0u);
     // gathers of the row below the block (ghost of row 0 at r_min: a copy,
     // or at the disc centre row 0 with directions turned by 4) and of the
@@ -698,9 +753,10 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
     const int rlo = r0 == 0 ? 0 : r0 - 1;
     const int tlo = r0 == 0 && dp->disc ? 4 : 0;
     const int rhi = min(r0 + 64, nr - 1);
-    const uint32_t vh1 = lane <= 32 ? (uint32_t)rlo * rowb + (uint32_t)shifted_plane(lane, tlo) * pb
-                                    : (uint32_t)rhi * rowb + (uint32_t)(lane - 33) * pb;
-    const uint32_t vh2 = lane < 2 ? (uint32_t)rhi * rowb + (uint32_t)(31 + lane) * pb : (uint32_t)rlo * rowb;
+    const uint32_t vh1 = lane <= 32 ? (uint32_t)rlo * rowb + (uint32_t)elem_of(shifted_plane(lane, tlo), 0, pt) * es
+                                    : (uint32_t)rhi * rowb + (uint32_t)elem_of(lane - 33, 0, pt) * es;
+    const uint32_t vh2 = lane < 2 ? (uint32_t)rhi * rowb + (uint32_t)elem_of(31 + lane, 0, pt) * es
+                                  : (uint32_t)rlo * rowb;
     const uint32_t vhl = lane == 1 ? (uint32_t)rhi * lrowb : (uint32_t)rlo * lrowb;
     real hf[2];
     double hlam;
@@ -789,7 +845,7 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
         }
         if (store) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) bstore(o[i], fout, vo, (uint32_t)(base + i) * pb);
+            for (int dd = 0; dd < 4; ++dd) bstore2(o[dd], o[dd + 4], fout, vo, rb + (uint32_t)(4 * (k - 1) + dd) * pb);
         }
     }
 
@@ -1005,7 +1061,8 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
     const bool store = S.useful;
     const int lane = S.lane;
     const uint32_t rowoff = (uint32_t)ir * S.row_bytes;
-    const uint32_t pb = opaque(S.plane_bytes);
+    const uint32_t pb = opaque(S.pair_bytes);
+    const uint32_t pairs = rowoff + S.rest_bytes;
 
     const real rest = C.rest(fc[0]);
     if (STAGEA)
@@ -1055,7 +1112,8 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
             for (int i = 0; i < 8; ++i) ga[base + i][lane] = o[i];
         } else if (store) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) bstore(o[i], S.fout, S.vo, rowoff + (uint32_t)(base + i) * pb);
+            for (int dd = 0; dd < 4; ++dd)
+                bstore2(o[dd], o[dd + 4], S.fout, S.vo2, pairs + (uint32_t)(4 * (k - 1) + dd) * pb);
         }
     }
 
@@ -1103,24 +1161,25 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     const real kcth = (real)ck.x, ksth = (real)ck.y;
     const real kctv[4] = {-ksth, (real)SQH * (kcth - ksth), kcth, (real)SQH * (kcth + ksth)};
 
-    const uint32_t es = (uint32_t)sizeof(real), rowb = S.row_bytes, pb = S.plane_bytes, lrowb = S.lrow_bytes;
+    const uint32_t es = (uint32_t)sizeof(real), rowb = S.row_bytes, lrowb = S.lrow_bytes;
+    const int64_t pt = dp->pitch;
     // radial neighbours: below row 0 the copy of row 0 (disc centre: with
     // directions turned by 4), above row nr - 1 the copy of row nr - 1
     const int rlo = max(r - 1, 0), rhi = min(r + 1, nr - 1);
     const bool turn = r == 0 && dp->disc;
     real x[NQ], nbr[NQ], nbt[NQ];
-    const uint32_t oc = (uint32_t)r * rowb + (uint32_t)pc * es;
+    const uint32_t oc = (uint32_t)r * rowb;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) bload(x[q], S.fin, oc + (uint32_t)q * pb, 0u);
+    for (int q = 0; q < NQ; ++q) bload(x[q], S.fin, oc + (uint32_t)elem_of(q, pc, pt) * es, 0u);
 #pragma unroll
     for (int q = 1; q < NQ; ++q) {
         const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8, dd = dir & 3, sgn = dir >> 2;
         const bool mr = crv[dd] >= (real)0, mt = ctv[dd] >= (real)0;
         const bool lower = sgn == 0 ? mr : !mr;
         const int plane = lower && turn ? base + ((dir + 4) & 7) : q;
-        bload(nbr[q], S.fin, (uint32_t)(lower ? rlo : rhi) * rowb + (uint32_t)plane * pb + (uint32_t)pc * es, 0u);
+        bload(nbr[q], S.fin, (uint32_t)(lower ? rlo : rhi) * rowb + (uint32_t)elem_of(plane, pc, pt) * es, 0u);
         const bool tl = sgn == 0 ? mt : !mt;
-        bload(nbt[q], S.fin, (uint32_t)r * rowb + (uint32_t)q * pb + (uint32_t)(tl ? pl : pr) * es, 0u);
+        bload(nbt[q], S.fin, (uint32_t)r * rowb + (uint32_t)elem_of(q, tl ? pl : pr, pt) * es, 0u);
     }
     double lc, lb, la, lL, lR;
     bload(lc, S.lin, (uint32_t)r * lrowb + (uint32_t)pc * 8u, 0u);
@@ -1446,10 +1505,10 @@ __global__ __launch_bounds__(BLOCK) void k_moments(SolveDesc d, int cur, double 
         const int jt = c - ir * d.nt;
         const real *fin = (const real *)d.f[cur];
         const int64_t idx = (int64_t)ir * d.pitch + jt;
-        const int64_t fidx = (int64_t)ir * d.rstride + jt;
+        const int64_t frow = (int64_t)ir * d.rstride;
         real f[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) f[q] = fin[q * d.plane + fidx];
+        for (int q = 0; q < NQ; ++q) f[q] = fin[frow + elem_of(q, jt, d.pitch)];
         real rho, jx, jy, e;
         raw_moments(f, rho, jx, jy, e);
         const double rd = (double)rho;
@@ -1486,10 +1545,10 @@ __global__ __launch_bounds__(BLOCK) void k_noneq(SolveDesc d, int cur, double *o
     const int ir = c / d.nt;
     const int jt = c - ir * d.nt;
     const real *fin = (const real *)d.f[cur];
-    const int64_t fidx = (int64_t)ir * d.rstride + jt;
+    const int64_t frow = (int64_t)ir * d.rstride;
     double f[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) f[q] = (double)fin[q * d.plane + fidx];
+    for (int q = 0; q < NQ; ++q) f[q] = (double)fin[frow + elem_of(q, jt, d.pitch)];
     double rho, jx, jy, e;
     raw_moments(f, rho, jx, jy, e);
     const double ux = jx / rho, uy = jy / rho;
@@ -1561,9 +1620,9 @@ __device__ __forceinline__ void store_eq(const SolveDesc &d, int cur, int64_t id
     const double ux = ur * cs.x - ut * cs.y, uy = ur * cs.y + ut * cs.x;
     real f[NQ];
     equilibrium<real>(d.A, (real)rho, (real)ux, (real)uy, (real)T, f);
-    real *fo = (real *)d.f[cur] + (idx / d.pitch) * d.rstride + jt;
+    real *fo = (real *)d.f[cur] + (idx / d.pitch) * d.rstride;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) fo[q * d.plane] = f[q];
+    for (int q = 0; q < NQ; ++q) fo[elem_of(q, jt, d.pitch)] = f[q];
 }
 
 template <typename real>
