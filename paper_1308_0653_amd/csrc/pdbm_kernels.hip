@@ -368,6 +368,7 @@ struct Strip {
     DescPtr dp;
     __amdgpu_buffer_rsrc_t fin, fout, lin, lout;
     uint32_t vo, vo2, vol;   // byte offsets of this lane's column: rest plane, pair, lambda
+    uint32_t vos, vos2, vols;  // ... of the lane's own column (the padding for periodic images)
     uint32_t vh1, vh2, vhl;  // byte offsets of this lane's halo gathers (plane and column)
     uint32_t row_bytes, lrow_bytes, rest_bytes, pair_bytes;
     uint32_t poff[4];     // rotated sectors: byte offset of the pair holding this lane's directions dd, dd + 4
@@ -399,6 +400,9 @@ struct Strip {
         vo = (uint32_t)pc * (uint32_t)sizeof(real);
         vo2 = 2u * vo;
         vol = (uint32_t)pc * 8u;
+        vos = (uint32_t)col * (uint32_t)sizeof(real);
+        vos2 = 2u * vos;
+        vols = (uint32_t)col * 8u;
         row_bytes = (uint32_t)dp->rstride * (uint32_t)sizeof(real);
         lrow_bytes = (uint32_t)dp->pitch * 8u;
         rest_bytes = (uint32_t)dp->plane * (uint32_t)sizeof(real);
@@ -547,8 +551,10 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
     const uint32_t pairs = rowoff + S.rest_bytes;
 
     // rest particle: no streaming
+    // every lane stores, periodic images into their own column of the row
+    // padding (see stage_row)
     const real rest = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * fc[0];
-    if (store) bstore(rest, S.fout, S.vo, rowoff);
+    bstore(rest, S.fout, S.vos, rowoff);
 
 #pragma unroll
     for (int k = 1; k <= 4; ++k) {
@@ -588,11 +594,12 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
                 const real nbt = tl ? left : right;
                 o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
             }
-            // stored lanes are never rotated sector images
-            if (dd % G == G - 1 && store) {
+            // lanes holding rotated sector images store into the padding
+            // too (their values are never read)
+            if (dd % G == G - 1) {
 #pragma unroll
                 for (int e = dd + 1 - G; e <= dd; ++e)
-                    bstore2(o[e], o[e + 4], S.fout, S.vo2, pairs + (uint32_t)(4 * (k - 1) + e) * pb);
+                    bstore2(o[e], o[e + 4], S.fout, S.vos2, pairs + (uint32_t)(4 * (k - 1) + e) * pb);
             }
         }
     }
@@ -613,7 +620,7 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
     const double lr = (urp >= 0.0) == lr_behind ? lbehind : lahead;
     const double lt = utp >= 0.0 ? lleft : lright;
     const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
-    if (store) bstore(lnew, S.lout, S.vol, (uint32_t)ir * S.lrow_bytes);
+    bstore(lnew, S.lout, S.vols, (uint32_t)ir * S.lrow_bytes);
 
     if (diag && store) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lc, ri * dp->dr * dp->dth, dp->Q);
 }
@@ -1064,11 +1071,15 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
     const uint32_t pb = opaque(S.pair_bytes);
     const uint32_t pairs = rowoff + S.rest_bytes;
 
+    // stage B stores from every lane, periodic images into their own
+    // column of the row padding (nothing reads it): no store sits under a
+    // lane mask, which keeps the exec-mask branches and their registers out
+    // of the row loop
     const real rest = C.rest(fc[0]);
     if (STAGEA)
         ga[0][lane] = rest;
-    else if (store)
-        bstore(rest, S.fout, S.vo, rowoff);
+    else
+        bstore(rest, S.fout, S.vos, rowoff);
 #pragma unroll
     for (int k = 1; k <= 4; ++k) {
         const real v = (real)speed(k);
@@ -1110,10 +1121,10 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
         if (STAGEA) {
 #pragma unroll
             for (int i = 0; i < 8; ++i) ga[base + i][lane] = o[i];
-        } else if (store) {
+        } else {
 #pragma unroll
             for (int dd = 0; dd < 4; ++dd)
-                bstore2(o[dd], o[dd + 4], S.fout, S.vo2, pairs + (uint32_t)(4 * (k - 1) + dd) * pb);
+                bstore2(o[dd], o[dd + 4], S.fout, S.vos2, pairs + (uint32_t)(4 * (k - 1) + dd) * pb);
         }
     }
 
@@ -1128,8 +1139,8 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
     const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
     if (STAGEA)
         lout = lnew;
-    else if (store)
-        bstore(lnew, S.lout, S.vol, (uint32_t)ir * S.lrow_bytes);
+    else
+        bstore(lnew, S.lout, S.vols, (uint32_t)ir * S.lrow_bytes);
 
     if (diag && store) diag_cell(red, (double)C.rho, uxd, uyd, C.Td, (double)C.e, lc, ri * dp->dr * dp->dth, dp->Q);
 }
