@@ -1,7 +1,9 @@
 // HIP kernels of libpdbm for gfx950 (MI355X).
 //
-// One cell per lane, structure-of-arrays f[q][ir][jt] so that a wavefront of
-// 64 consecutive theta cells reads 64 contiguous values per velocity plane.
+// One cell per lane.  Within an r row, f holds the rest particle's plane and
+// the 16 pairs of opposite directions interleaved per column (elem_of), so
+// that a wavefront of 64 consecutive theta cells reads one contiguous block
+// per plane or pair, one 8- or 16-byte access per lane for a pair.
 // The collision is evaluated in the Cartesian frame: f^eq depends on v.u and
 // |u|^2 only, which are the same in polar and Cartesian components, so the
 // 33 velocities are compile-time constants (speeds 0, 1.5, 3.5, 7.5, 12.5 of
@@ -361,8 +363,9 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x)
 // three gathered loads per row, lane q of which fetches one (plane, side)
 // pair, and are moved into lane 0 or 63 by readlane.  Strips start on
 // 64-column boundaries and rows are padded to a multiple of 64, so every
-// store of a velocity plane covers whole cache lines.  The second row ahead
-// is requested a whole row of compute before it is first needed.
+// store of a plane or pair covers whole cache lines; lanes past the last
+// column own a padding column.  The second row ahead is requested a whole row
+// of compute before it is first needed.
 template <typename real, bool ROT>
 struct Strip {
     DescPtr dp;
