@@ -967,10 +967,16 @@ struct Cell {
     real F[5];
     EqPoly<real> EP;
 
+    Cell() = default;
     __device__ __forceinline__ Cell(DescPtr dp, const real x[NQ], double lc)
     {
         real jx, jy;
         raw_moments(x, rho, jx, jy, e);
+        init_moments(dp, jx, jy, lc);
+    }
+    // from rho, e (members) and the momentum jx, jy
+    __device__ __forceinline__ void init_moments(DescPtr dp, real jx, real jy, double lc)
+    {
         const real irho = (real)1 / rho;
         ux = jx * irho;
         uy = jy * irho;
@@ -1148,19 +1154,35 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
     if (diag && store) diag_cell(red, (double)C.rho, uxd, uyd, C.Td, (double)C.e, lc, ri * dp->dr * dp->dth, dp->Q);
 }
 
+// The value the other lane of a lane pair (lanes 2m, 2m + 1) holds.
+__device__ __forceinline__ float pair_swap(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double pair_swap(double v)
+{
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xf, 0xf, false),
+                            __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xf, 0xf, false));
+}
+
 // The intermediate state at the columns bordering strip `strip`, c0 - 1
 // (left) and c0 + 64 (right) as periodic images, for the rows [i0, i1) of the
-// block: lane 32 side + e takes row i0 + e of its side.  Each lane gathers its
-// cell and the cell's upwind neighbours (radial ghost rules of Sec. II.D
-// included) and updates it as stage A of the strip owning the column does.
-// Of each opposite pair of directions it keeps the one that lane 0 (left
-// side) or lane 63 (right side) takes from there, and lambda.
+// block.  Two lanes take one cell: lane 32 side + 2 e + h takes row i0 + e of
+// its side, h = 0 the speeds 1 and 2 (and the rest particle), h = 1 the
+// speeds 3 and 4.  Each lane gathers its pairs of the cell and of the cell's
+// upwind neighbours (radial ghost rules of Sec. II.D included), one access
+// per pair; the two lanes add up their partial moments, and each updates its
+// pairs as stage A of the strip owning the column does.  Of each opposite
+// pair of directions it keeps the one that lane 0 (left side) or lane 63
+// (right side) takes from there; the first lane of the two keeps lambda.
+// Every lane runs every instruction up to the final stores (the moment
+// exchange is a lane shift).
 template <typename real>
 __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int strip, int i0, int i1,
                                            real (*ef)[FUSE_ROWS][16], double (*el)[FUSE_ROWS])
 {
     const DescPtr dp = S.dp;
-    const int lane = S.lane, side = lane >> 5, e = lane & 31;
+    const int lane = S.lane, side = lane >> 5, e = (lane >> 1) & 15, h = lane & 1;
     const int count = i1 - i0;
     const int nr = dp->nr, nt = dp->nt;
     const int r = i0 + min(e, count - 1);  // lanes past the block repeat its last row
@@ -1176,24 +1198,35 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     const real kctv[4] = {-ksth, (real)SQH * (kcth - ksth), kcth, (real)SQH * (kcth + ksth)};
 
     const uint32_t es = (uint32_t)sizeof(real), rowb = S.row_bytes, lrowb = S.lrow_bytes;
-    const int64_t pt = dp->pitch;
     // radial neighbours: below row 0 the copy of row 0 (disc centre: with
-    // directions turned by 4), above row nr - 1 the copy of row nr - 1
+    // directions turned by 4, i.e. the members of each pair swapped), above
+    // row nr - 1 the copy of row nr - 1
     const int rlo = max(r - 1, 0), rhi = min(r + 1, nr - 1);
     const bool turn = r == 0 && dp->disc;
-    real x[NQ], nbr[NQ], nbt[NQ];
-    const uint32_t oc = (uint32_t)r * rowb;
+    const uint32_t orow = (uint32_t)r * rowb, olo = (uint32_t)rlo * rowb, ohi = (uint32_t)rhi * rowb;
+    const uint32_t cc = 2u * (uint32_t)pc * es, cl = 2u * (uint32_t)pl * es, cr = 2u * (uint32_t)pr * es;
+    // this lane's pairs 8 h .. 8 h + 7 (speeds 2 h + 1, 2 h + 2): directions
+    // dd of pair i in x[i], dd + 4 in x[i + 8]
+    real x[16], nbr[16], nbt[16], x0;
+    bload(x0, S.fin, orow + (uint32_t)pc * es, 0u);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) bload(x[q], S.fin, oc + (uint32_t)elem_of(q, pc, pt) * es, 0u);
-#pragma unroll
-    for (int q = 1; q < NQ; ++q) {
-        const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8, dd = dir & 3, sgn = dir >> 2;
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t po = S.rest_bytes + (uint32_t)(8 * h + i) * S.pair_bytes;
+        const int dd = i & 3;
+        real lo0, lo1, hi0, hi1, l0, l1, r0, r1;
+        bload2(x[i], x[i + 8], S.fin, orow + cc + po, 0u);
+        bload2(lo0, lo1, S.fin, olo + cc + po, 0u);
+        bload2(hi0, hi1, S.fin, ohi + cc + po, 0u);
+        bload2(l0, l1, S.fin, orow + cl + po, 0u);
+        bload2(r0, r1, S.fin, orow + cr + po, 0u);
+        const real t0 = turn ? lo1 : lo0, t1 = turn ? lo0 : lo1;
         const bool mr = crv[dd] >= (real)0, mt = ctv[dd] >= (real)0;
-        const bool lower = sgn == 0 ? mr : !mr;
-        const int plane = lower && turn ? base + ((dir + 4) & 7) : q;
-        bload(nbr[q], S.fin, (uint32_t)(lower ? rlo : rhi) * rowb + (uint32_t)elem_of(plane, pc, pt) * es, 0u);
-        const bool tl = sgn == 0 ? mt : !mt;
-        bload(nbt[q], S.fin, (uint32_t)r * rowb + (uint32_t)elem_of(q, tl ? pl : pr, pt) * es, 0u);
+        // direction dd takes the lower row if mr and the left column if mt,
+        // dd + 4 the other ones
+        nbr[i] = mr ? t0 : hi0;
+        nbr[i + 8] = mr ? hi1 : t1;
+        nbt[i] = mt ? l0 : r0;
+        nbt[i + 8] = mt ? r1 : l1;
     }
     double lc, lb, la, lL, lR;
     bload(lc, S.lin, (uint32_t)r * lrowb + (uint32_t)pc * 8u, 0u);
@@ -1202,32 +1235,49 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     bload(lL, S.lin, (uint32_t)r * lrowb + (uint32_t)pl * 8u, 0u);
     bload(lR, S.lin, (uint32_t)r * lrowb + (uint32_t)pr * 8u, 0u);
 
-    const Cell<real> C(dp, x, lc);
+    // moments: this lane's two rings (summed as raw_moments does), then the
+    // other lane's added
+    const real va = h == 0 ? (real)speed(1) : (real)speed(3), vb = h == 0 ? (real)speed(2) : (real)speed(4);
+    real rho = h == 0 ? x0 : (real)0, jx = 0, jy = 0, en = 0;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+        const real *g = x + 4 * kk;  // directions 0..3 at g[0..3], 4..7 at g[8..11]
+        const real v = kk == 0 ? va : vb;
+        const real ring = ((g[0] + g[8]) + (g[2] + g[10])) + ((g[1] + g[9]) + (g[3] + g[11]));
+        const real a15 = g[1] - g[9], a37 = g[3] - g[11];
+        const real X = (g[0] - g[8]) + (real)SQH * (a15 - a37);
+        const real Y = (g[2] - g[10]) + (real)SQH * (a15 + a37);
+        rho += ring;
+        jx += v * X;
+        jy += v * Y;
+        en += (real)0.5 * v * v * ring;
+    }
+    Cell<real> C;
+    C.rho = rho + pair_swap(rho);
+    C.e = en + pair_swap(en);
+    C.init_moments(dp, jx + pair_swap(jx), jy + pair_swap(jy), lc);
+
     const double ri = dp->r_min + ((double)r + 0.5) * dp->dr;
     const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
-    real g[NQ];
-    g[0] = C.rest(x[0]);
+    real g[16];
 #pragma unroll
-    for (int k = 1; k <= 4; ++k) {
-        const real v = (real)speed(k);
-        const real rF = C.rho * C.F[k];
+    for (int kk = 0; kk < 2; ++kk) {
+        const real v = kk == 0 ? va : vb;
+        const real Fk = h == 0 ? C.F[1 + kk] : C.F[3 + kk];
+        const real rF = C.rho * Fk;
         const real Ak = C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T);
-        const int base = 1 + 8 * (k - 1);
 #pragma unroll
         for (int dd = 0; dd < 4; ++dd) {
+            const int i = 4 * kk + dd;
             const real z = v * C.EP.w(dd);
             real pp, pm;
             C.EP.eval(z, pp, pm);
             const real bz = C.Bz * z;
             const real acr = fabs(crv[dd]) * kr, act = fabs(ctv[dd]) * kt;
-#pragma unroll
-            for (int sgn = 0; sgn < 2; ++sgn) {
-                const int q = base + dd + 4 * sgn;
-                const real xq = x[q];
-                const real coll =
-                    sgn == 0 ? rF * pp * (Ak + bz) + C.omega * xq : rF * pm * (Ak - bz) + C.omega * xq;
-                g[q] = coll - v * (acr * (xq - nbr[q]) + act * (xq - nbt[q]));
-            }
+            const real c0v = rF * pp * (Ak + bz) + C.omega * x[i];
+            const real c1v = rF * pm * (Ak - bz) + C.omega * x[i + 8];
+            g[i] = c0v - v * (acr * (x[i] - nbr[i]) + act * (x[i] - nbt[i]));
+            g[i + 8] = c1v - v * (acr * (x[i + 8] - nbr[i + 8]) + act * (x[i + 8] - nbt[i + 8]));
         }
     }
     const double uxd = (double)C.ux, uyd = (double)C.uy;
@@ -1239,14 +1289,12 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
         C.reacted(dp, lc) - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
     if (e < count) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int dd = 0; dd < 4; ++dd) {
-                const bool first = (kctv[dd] >= (real)0) != (side == 1);  // keep direction dd, else dd + 4
-                const int q = 1 + 8 * k + dd;
-                ef[side][e][4 * k + dd] = first ? g[q] : g[q + 4];
-            }
-        el[side][e] = lnew;
+        for (int i = 0; i < 8; ++i) {
+            const int dd = i & 3;
+            const bool first = (kctv[dd] >= (real)0) != (side == 1);  // keep direction dd, else dd + 4
+            ef[side][e][8 * h + i] = first ? g[i] : g[i + 8];
+        }
+        if (h == 0) el[side][e] = lnew;
     }
 }
 
