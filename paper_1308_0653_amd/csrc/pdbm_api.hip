@@ -440,7 +440,7 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
     const bool pairs = s.fusable();
     for (int64_t i = 0; i < nsteps;) {
         if (pairs && nsteps - i >= 2) {
-            HIPCHK(launch_step2(s.dd, s.waves(), s.step, s.flip, s.fp32, h->st));
+            HIPCHK(launch_step2(s.dd, s.waves(), s.step, s.flip, h->st));
             s.step += 2;
             s.flip ^= 1;
             i += 2;

@@ -1751,14 +1751,11 @@ hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, c
     return hipGetLastError();
 }
 
-hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, bool fp32, hipStream_t st)
+hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, hipStream_t st)
 {
     const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0) return hipSuccess;
-    if (fp32)
-        hipLaunchKernelGGL(k_step2<float>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
-    else
-        hipLaunchKernelGGL(k_step2<double>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
+    hipLaunchKernelGGL(k_step2<double>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
     return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
 """Two steps per launch against one step per launch.
 
-Solver.step(n) advances a full-annulus solve with ntheta > 1 in pairs of
-steps, each pair in one pass over f (k_step2); step(1) always takes the
-one-step kernel.  Both do the same arithmetic per cell in the same order, so
+Solver.step(n) advances a full-annulus float64 solve with ntheta > 1 in
+pairs of steps, each pair in one pass over f (k_step2); step(1) always takes
+the one-step kernel, and float32 solves always step one at a time (their
+cases here check the step loop itself).  Both do the same arithmetic per cell in the same order, so
 their states agree to rounding.  The cases cover strip and row-block edges
 (blocks of one row up to the 16-row limit, marched both ways), the disc
 centre, both precisions, odd step counts (pairs and one single step), the
