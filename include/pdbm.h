@@ -166,7 +166,11 @@ int pdbm_set_fields(pdbm_solver *s, const double *fields);
 
 /* Enqueues `nsteps` time steps on the solver's stream and returns without
  * waiting.  Every diag_every-th step also records the drift report of the
- * state it starts from. */
+ * state it starts from.  Float64 solves of the full annulus with ntheta > 1
+ * take the steps two per launch (one pass over f for both; the result equals
+ * that of single steps to rounding), and an odd count ends with a single
+ * step; the states after every call are those of Sec. II.C's scheme either
+ * way. */
 int pdbm_step(pdbm_solver *s, int64_t nsteps);
 
 /* Number of steps taken so far (host-side counter). */
