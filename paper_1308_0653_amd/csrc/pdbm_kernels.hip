@@ -955,7 +955,8 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
 // strip; the wavefront computes those cells itself at the start
 // (edge_cells), as the adjacent strips do in their own stage A.  A block of
 // R rows runs stage A on R + 2 rows and reads R + 4 rows of f, so each f
-// value is read about once and written once per two steps.
+// value is read about 1.3 times (block boundaries, edge-cell gathers) and
+// written once per two steps.
 
 // Per-cell quantities of one update (Sec. II.B-C): moments, F_k(T), the f^eq
 // polynomial and the BGK / chemical factors, evaluated as update_row does.
@@ -1332,8 +1333,9 @@ __device__ __forceinline__ void fill_behind(real (*behind)[64], const real x[NQ]
 // count rows in marching order from the first row of the block (p = 0);
 // stage A runs on positions -1 .. R where they are grid rows, stage B on
 // 0 .. R - 1, one position behind stage A.  LDS per wavefront: the compact
-// rows behind of f (fb) and of g (gb), the full row of g just computed (ga)
-// and the edge cells.
+// rows behind of f (fb) and of g (gb), the full row of g just computed (ga),
+// the edge cells (ef, el) and the gathered halo values of stage A's row
+// (hb, hbl).
 template <typename real>
 __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
                                        real (*fb)[64], real (*gb)[64], real (*ga)[64], real (*ef)[FUSE_ROWS][16],
