@@ -495,6 +495,67 @@ __device__ __forceinline__ real halo_right(const real h[2], int q)
     return q <= 30 ? lane_value(h[0], 33 + q) : lane_value(h[1], q - 31);
 }
 
+// Per-cell quantities of one update (Sec. II.B-C): moments, F_k(T), the f^eq
+// polynomial and the BGK / chemical factors (the Cochran rate gated by the
+// ignition temperature, in float64; M dt = f^eq beta (|v - u|^2 - 2T) with
+// beta = Q R dt / (2 T^2), D = 2).
+template <typename real>
+struct Cell {
+    real rho, e, ux, uy, u2, T, beta, omega, keep, Bz;
+    double Td, a, b;
+    bool on;
+    real F[5];
+    EqPoly<real> EP;
+
+    Cell() = default;
+    __device__ __forceinline__ Cell(DescPtr dp, const real x[NQ], double lc)
+    {
+        real jx, jy;
+        raw_moments(x, rho, jx, jy, e);
+        init_moments(dp, jx, jy, lc);
+    }
+    // from rho, e (members) and the momentum jx, jy
+    __device__ __forceinline__ void init_moments(DescPtr dp, real jx, real jy, double lc)
+    {
+        const real irho = (real)1 / rho;
+        ux = jx * irho;
+        uy = jy * irho;
+        u2 = ux * ux + uy * uy;
+        T = e * irho - (real)0.5 * u2;
+        Td = (double)T;
+        weights(dp->A, Td, F);
+        EP = EqPoly<real>(ux, uy, u2, T);
+        a = 0.0;
+        b = 0.0;
+        double R = 0.0;
+        on = dp->reacts && Td > dp->T_th;
+        if (on) {
+            const double p = (double)rho * Td;
+            a = dp->w1 * ipow(p, dp->m);
+            b = dp->w2 * ipow(p, dp->n);
+            R = (1.0 - lc) * (a + b * lc);
+        }
+        beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
+        omega = (real)dp->omega;
+        keep = (real)1 - omega;
+        Bz = (real)-2 * beta * T;
+    }
+    // the rest particle after collision (it does not stream)
+    __device__ __forceinline__ real rest(real x0) const
+    {
+        return rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * x0;
+    }
+    // lambda after the closed-form Cochran step
+    __device__ __forceinline__ double reacted(DescPtr dp, double lc) const
+    {
+        if (on && a + b > 0.0) {
+            const double q1 = (1.0 - lc) * exp(-(a + b) * dp->dt);
+            return 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
+        }
+        return lc;
+    }
+};
+
 // One row of one strip: moments, F_k(T), f^eq, BGK + chemical term, Cochran
 // lambda, donor-cell fluxes of f and lambda.  fc: row i.  Marching outward
 // (down = false): prev (LDS, this lane's column) holds row i-1 and fn row
@@ -509,34 +570,13 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
                                            bool lr_behind, double csx, double csy, double red[5], bool diag)
 {
     const DescPtr dp = S.dp;
-    // (1) moments
-    real rho, jx, jy, e;
-    raw_moments(fc, rho, jx, jy, e);
-    const real irho = (real)1 / rho;
-    const real ux = jx * irho, uy = jy * irho;
-    const real u2 = ux * ux + uy * uy;
-    const real T = e * irho - (real)0.5 * u2;
-    const double Td = (double)T;
-
-    // (2) weights and f^eq polynomial
-    real F[5];
-    weights(dp->A, Td, F);
-    const EqPoly<real> EP(ux, uy, u2, T);
-
-    // (3) Cochran rate, gated by the ignition temperature (float64)
-    double a = 0.0, b = 0.0, R = 0.0;
-    const bool on = dp->reacts && Td > dp->T_th;
-    if (on) {
-        const double p = (double)rho * Td;
-        a = dp->w1 * ipow(p, dp->m);
-        b = dp->w2 * ipow(p, dp->n);
-        R = (1.0 - lc) * (a + b * lc);
-    }
-    // M dt = f^eq * beta * (|v-u|^2 - 2T), beta = Q R dt / (2 T^2) (D = 2)
-    const real beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
-    const real omega = (real)dp->omega;
-    const real keep = (real)1 - omega;
-    const real Bz = (real)-2 * beta * T;
+    // (1)-(3) moments, weights, f^eq polynomial, BGK and chemical factors
+    const Cell<real> C(dp, fc, lc);
+    const real rho = C.rho, e = C.e, ux = C.ux, uy = C.uy, u2 = C.u2, T = C.T;
+    const real beta = C.beta, omega = C.omega, keep = C.keep, Bz = C.Bz;
+    const double Td = C.Td;
+    const real *F = C.F;
+    const EqPoly<real> &EP = C.EP;
 
     // azimuthal Courant magnitudes of this row (the geometric 1/r term)
     const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
@@ -611,11 +651,7 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
     const double uxd = (double)ux, uyd = (double)uy;
     const double urp = uxd * csx + uyd * csy;
     const double utp = -uxd * csy + uyd * csx;
-    double lreac = lc;
-    if (on && a + b > 0.0) {
-        const double q1 = (1.0 - lc) * exp(-(a + b) * dp->dt);
-        lreac = 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
-    }
+    const double lreac = C.reacted(dp, lc);
     const double sll = from_left(lc), slr = from_right(lc);
     const double hll = lane_value(hlam, 0), hlr = lane_value(hlam, 1);
     const double lleft = lane == 0 ? hll : sll;
@@ -774,31 +810,13 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
     bload(hf[1], fin, vh2, 0u);
     bload(hlam, lin, vhl, 0u);
 
-    // (1) moments
-    real rho, jx, jy, e;
-    raw_moments(fc, rho, jx, jy, e);
-    const real irho = (real)1 / rho;
-    const real ux = jx * irho, uy = jy * irho;
-    const real u2 = ux * ux + uy * uy;
-    const real T = e * irho - (real)0.5 * u2;
-    const double Td = (double)T;
-    // (2) weights and f^eq polynomial
-    real F[5];
-    weights(dp->A, Td, F);
-    const EqPoly<real> EP(ux, uy, u2, T);
-    // (3) Cochran rate, gated by the ignition temperature (float64)
-    double a = 0.0, b = 0.0, R = 0.0;
-    const bool on = dp->reacts && Td > dp->T_th;
-    if (on) {
-        const double p = (double)rho * Td;
-        a = dp->w1 * ipow(p, dp->m);
-        b = dp->w2 * ipow(p, dp->n);
-        R = (1.0 - lc) * (a + b * lc);
-    }
-    const real beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
-    const real omega = (real)dp->omega;
-    const real keep = (real)1 - omega;
-    const real Bz = (real)-2 * beta * T;
+    // (1)-(3) moments, weights, f^eq polynomial, BGK and chemical factors
+    const Cell<real> C(dp, fc, lc);
+    const real rho = C.rho, e = C.e, ux = C.ux, uy = C.uy, u2 = C.u2, T = C.T;
+    const real beta = C.beta, omega = C.omega, keep = C.keep, Bz = C.Bz;
+    const double Td = C.Td;
+    const real *F = C.F;
+    const EqPoly<real> &EP = C.EP;
 
     // polar components of directions dd = 0..3 at theta_0 (dd+4 is the negative)
     const double2 cs = dp->cs[0];
@@ -863,11 +881,7 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
     // azimuthal neighbour of the single column is the cell itself)
     const double uxd = (double)ux, uyd = (double)uy;
     const double urp = uxd * cs.x + uyd * cs.y;
-    double lreac = lc;
-    if (on && a + b > 0.0) {
-        const double q1 = (1.0 - lc) * exp(-(a + b) * dp->dt);
-        lreac = 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
-    }
+    const double lreac = C.reacted(dp, lc);
     const double sll = from_left(lc), slr = from_right(lc);
     const double hll = lane_value(hlam, 0), hlr = lane_value(hlam, 1);
     const double llow = lane == 0 ? hll : sll;
@@ -957,65 +971,6 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
 // R rows runs stage A on R + 2 rows and reads R + 4 rows of f, so each f
 // value is read about 1.3 times (block boundaries, edge-cell gathers) and
 // written once per two steps.
-
-// Per-cell quantities of one update (Sec. II.B-C): moments, F_k(T), the f^eq
-// polynomial and the BGK / chemical factors, evaluated as update_row does.
-template <typename real>
-struct Cell {
-    real rho, e, ux, uy, u2, T, beta, omega, keep, Bz;
-    double Td, a, b;
-    bool on;
-    real F[5];
-    EqPoly<real> EP;
-
-    Cell() = default;
-    __device__ __forceinline__ Cell(DescPtr dp, const real x[NQ], double lc)
-    {
-        real jx, jy;
-        raw_moments(x, rho, jx, jy, e);
-        init_moments(dp, jx, jy, lc);
-    }
-    // from rho, e (members) and the momentum jx, jy
-    __device__ __forceinline__ void init_moments(DescPtr dp, real jx, real jy, double lc)
-    {
-        const real irho = (real)1 / rho;
-        ux = jx * irho;
-        uy = jy * irho;
-        u2 = ux * ux + uy * uy;
-        T = e * irho - (real)0.5 * u2;
-        Td = (double)T;
-        weights(dp->A, Td, F);
-        EP = EqPoly<real>(ux, uy, u2, T);
-        a = 0.0;
-        b = 0.0;
-        double R = 0.0;
-        on = dp->reacts && Td > dp->T_th;
-        if (on) {
-            const double p = (double)rho * Td;
-            a = dp->w1 * ipow(p, dp->m);
-            b = dp->w2 * ipow(p, dp->n);
-            R = (1.0 - lc) * (a + b * lc);
-        }
-        beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
-        omega = (real)dp->omega;
-        keep = (real)1 - omega;
-        Bz = (real)-2 * beta * T;
-    }
-    // the rest particle after collision (it does not stream)
-    __device__ __forceinline__ real rest(real x0) const
-    {
-        return rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * x0;
-    }
-    // lambda after the closed-form Cochran step
-    __device__ __forceinline__ double reacted(DescPtr dp, double lc) const
-    {
-        if (on && a + b > 0.0) {
-            const double q1 = (1.0 - lc) * exp(-(a + b) * dp->dt);
-            return 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
-        }
-        return lc;
-    }
-};
 
 // Azimuthal neighbours of lanes 0 and 63 for stage A: the three gathered
 // loads of a row of the input state, written to an LDS row and read back by
