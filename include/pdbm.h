@@ -16,7 +16,8 @@
  *      geometric 1/r term), a periodic theta halo and radial boundaries
  *      (Sec. II.C-D); the reaction progress lambda is integrated in closed
  *      form and advected upwind by the cell's own u (Sec. III.A).
- * All four run in one fused kernel launch per step on the caller's stream.
+ * All four run in one fused kernel launch per step on the caller's stream
+ * (float64 full-annulus solves: one launch per two steps, see pdbm_step).
  *
  * Conventions
  *   - Every entry point returns 0 (PDBM_OK) or a negative PDBM_E* code;
@@ -32,6 +33,13 @@
  *     padding: [F][nr][ntheta].
  *   - A solver is driven from one host thread at a time.  The server entry
  *     points are thread-safe.
+ *
+ * Environment (read once per process; for measurement and tuning)
+ *   PDBM_FUSE=0            every launch of pdbm_step takes a single step.
+ *   PDBM_ROWS_PER_WAVE=n   r rows per wavefront of single solves (created
+ *                          after it is set); above 16 disables two-step
+ *                          launches.
+ *   PDBM_BATCH_ROWS=n      r rows per wavefront of packed launches (4).
  */
 #ifndef PDBM_H
 #define PDBM_H

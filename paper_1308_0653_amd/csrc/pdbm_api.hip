@@ -67,10 +67,11 @@ Layout pdbm::layout_of(const pdbm_params &p, int rows)
 }
 
 // Rows per wavefront: just enough wavefronts for one resident wave of the
-// whole grid (256 CUs x 4 SIMDs x the step kernel's occupancy: 1 wavefront
+// whole grid (256 CUs x 4 SIMDs x the step kernels' occupancy: 1 wavefront
 // per SIMD in float64, 2 in float32), so that every wavefront marches the
-// longest possible column and none waits for a second round.
-// PDBM_ROWS_PER_WAVE overrides it (tuning).
+// longest possible column and none waits for a second round; at most
+// FUSE_ROWS (the two-step kernel's limit), so grids of more than 16 rows per
+// SIMD run several rounds.  PDBM_ROWS_PER_WAVE overrides it (tuning).
 int pdbm::rows_per_wave(const pdbm_params &p)
 {
     const int nr = p.nr, nt = p.ntheta;
