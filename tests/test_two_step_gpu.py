@@ -46,8 +46,9 @@ TOL = {P.PDBM_FP64: 1e-13, P.PDBM_FP32: 1e-6}
 
 
 @pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
-@pytest.mark.parametrize("nr,nt,r_min", [(1, 64, 0.3), (2, 65, 0.3), (5, 2, 0.3), (33, 65, 0.3), (17, 200, 0.0),
-                                         (40, 130, 0.0), (64, 64, 0.3), (8192, 130, 0.3)])
+@pytest.mark.parametrize("nr,nt,r_min", [(1, 64, 0.3), (1, 64, 0.0), (2, 65, 0.3), (2, 130, 0.0), (5, 2, 0.3),
+                                         (33, 65, 0.3), (17, 200, 0.0), (40, 130, 0.0), (64, 64, 0.3),
+                                         (8192, 130, 0.3)])
 def test_pairs_match_single_steps(precision, nr, nt, r_min):
     w = _case(nr, nt, r_min)
     n = 7  # three pairs and one single step
