@@ -1,0 +1,593 @@
+// Device code shared by the kernels of libpdbm for gfx950 (MI355X): the
+// per-cell arithmetic of the method, wavefront reductions, lane shifts, raw
+// buffer access and the wavefront strip over the paired f layout.
+//
+// One cell per lane.  Within an r row, f holds the rest particle's plane and
+// the 16 pairs of opposite directions interleaved per column (elem_of), so
+// that a wavefront of 64 consecutive theta cells reads one contiguous block
+// per plane or pair, one 8- or 16-byte access per lane for a pair.
+// The collision is evaluated in the Cartesian frame: f^eq depends on v.u and
+// |u|^2 only, which are the same in polar and Cartesian components, so the
+// 33 velocities are compile-time constants (speeds 0, 1.5, 3.5, 7.5, 12.5 of
+// Sec. II.B, directions i*pi/4 fixed in the Cartesian frame).  Polar
+// components are needed only for the Courant numbers and for u_r, u_theta.
+
+#pragma once
+
+#include <math.h>
+
+#include "pdbm_internal.h"
+
+namespace pdbm {
+namespace {
+
+constexpr double SQH = 0.70710678118654752440;  // cos(pi/4) = sin(pi/4)
+
+__device__ __forceinline__ constexpr double speed(int k)
+{
+    return k == 1 ? 1.5 : k == 2 ? 3.5 : k == 3 ? 7.5 : 12.5;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Renumber them so that each XCD walks one contiguous range of
+// tiles: neighbouring rows of the stencil then meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb)
+{
+    const int q = nb / NXCD, r = nb % NXCD;
+    const int x = bid % NXCD, s = bid / NXCD;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
+__device__ __forceinline__ double ipow(double x, int e)
+{
+    double y = 1.0;
+    for (int i = 0; i < e; ++i) y *= x;
+    return y;
+}
+
+// F_k(T), k = 0..4, from the moment-inversion matrix (Horner in T, float64).
+template <typename real>
+__device__ __forceinline__ void weights(const double *A, double T, real F[5])
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double v = T * (A[4 * k] + T * (A[4 * k + 1] + T * (A[4 * k + 2] + T * A[4 * k + 3])));
+        F[k + 1] = (real)v;
+        s += v;
+    }
+    F[0] = (real)(1.0 - 8.0 * s);
+}
+
+// rho, rho*u (Cartesian), and e = sum f |v|^2 / 2 of one cell.
+template <typename real>
+__device__ __forceinline__ void raw_moments(const real f[NQ], real &rho, real &jx, real &jy, real &e)
+{
+    rho = f[0];
+    jx = 0;
+    jy = 0;
+    e = 0;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real *g = f + 1 + 8 * (k - 1);
+        const real v = (real)speed(k);
+        const real ring = ((g[0] + g[4]) + (g[2] + g[6])) + ((g[1] + g[5]) + (g[3] + g[7]));
+        const real a15 = g[1] - g[5], a37 = g[3] - g[7];
+        const real X = (g[0] - g[4]) + (real)SQH * (a15 - a37);
+        const real Y = (g[2] - g[6]) + (real)SQH * (a15 + a37);
+        rho += ring;
+        jx += v * X;
+        jy += v * Y;
+        e += (real)(0.5 * speed(k) * speed(k)) * ring;
+    }
+}
+
+// Coefficients of the f^eq polynomial in z = v.u / T (Sec. II.B):
+// P(z) = (1 - a + a^2/2) + z (1 - a) + z^2 (1 - a)/2 + z^3/6 + z^4/24, a = u^2/(2T)
+template <typename real>
+struct EqPoly {
+    real c0, c1, c2, wx, wy;
+    EqPoly() = default;
+    __device__ __forceinline__ EqPoly(real ux, real uy, real u2, real T)
+    {
+        const real iT = (real)1 / T;
+        const real a = (real)0.5 * u2 * iT;
+        c0 = (real)1 - a + (real)0.5 * a * a;
+        c1 = (real)1 - a;
+        c2 = (real)0.5 * c1;
+        wx = ux * iT;
+        wy = uy * iT;
+    }
+    // projection of direction d (0..3) on u, divided by T; d+4 is its negative
+    __device__ __forceinline__ real w(int d) const
+    {
+        return d == 0 ? wx : d == 1 ? (real)SQH * (wx + wy) : d == 2 ? wy : (real)SQH * (wy - wx);
+    }
+    // P(z) and P(-z) from the even and odd parts
+    __device__ __forceinline__ void eval(real z, real &pp, real &pm) const
+    {
+        const real z2 = z * z;
+        const real ev = c0 + z2 * (c2 + z2 * (real)(1.0 / 24.0));
+        const real od = z * (c1 + z2 * (real)(1.0 / 6.0));
+        pp = ev + od;
+        pm = ev - od;
+    }
+};
+
+template <typename real>
+__device__ __forceinline__ void equilibrium(const double *A, real rho, real ux, real uy, real T, real f[NQ])
+{
+    real F[5];
+    weights(A, (double)T, F);
+    const real u2 = ux * ux + uy * uy;
+    const EqPoly<real> P(ux, uy, u2, T);
+    f[0] = rho * F[0] * P.c0;
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real rF = rho * F[k];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            real pp, pm;
+            P.eval((real)speed(k) * P.w(d), pp, pm);
+            f[1 + 8 * (k - 1) + d] = rF * pp;
+            f[1 + 8 * (k - 1) + d + 4] = rF * pm;
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Sums v[0..4] over the workgroup; the result is valid in thread 0.
+__device__ __forceinline__ void block_sum5(double v[5])
+{
+    __shared__ double lds[BLOCK / 64][5];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) v[i] = wave_sum(v[i]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) lds[w][i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            double s = lds[0][i];
+            for (int j = 1; j < BLOCK / 64; ++j) s += lds[j][i];
+            v[i] = s;
+        }
+}
+
+// Per-block partial sums, then the last block to finish adds the partials in
+// a fixed order (deterministic, no floating-point atomics) and writes the
+// record.  Must be reached by every thread of every block.
+__device__ void diag_reduce(const DiagCtl &dc, double v[5], int tile, int nb)
+{
+    __shared__ int last;
+    block_sum5(v);
+    if (threadIdx.x == 0) {
+        double *p = dc.partials + 5 * (size_t)tile;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) p[i] = v[i];
+        __threadfence();
+        const unsigned done = atomicAdd(dc.counter, 1u);
+        last = done == (unsigned)(nb - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += BLOCK)
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            acc[i] += __hip_atomic_load(dc.partials + 5 * (size_t)b + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    block_sum5(acc);
+    if (threadIdx.x == 0) {
+        pdbm_diag r;
+        r.step = dc.step;
+        r.mass = acc[0];
+        r.energy = acc[1];
+        r.chem = acc[2];
+        r.n_nonfinite = (int64_t)acc[3];
+        r.n_nonphys = (int64_t)acc[4];
+        *dc.out = r;
+        __hip_atomic_store(dc.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Contribution of one cell to the drift report.
+__device__ __forceinline__ void diag_cell(double v[5], double rho, double ux, double uy, double T, double e, double lam,
+                                          double w, double Q)
+{
+    const bool finite = isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy) && isfinite(lam);
+    if (!finite) {
+        v[3] += 1.0;
+        return;
+    }
+    if (rho <= 0.0 || T <= 0.0) v[4] += 1.0;
+    v[0] += rho * w;
+    v[1] += e * w;
+    v[2] += rho * Q * (1.0 - lam) * w;
+}
+
+// ------------------------------------------------- wavefront strips --
+// Cross-lane moves within a wavefront (DPP wave shifts): the value held by
+// lane-1 (from_left) and by lane+1 (from_right).  Lanes 0 / 63 receive 0 and
+// take their neighbours from the halo gathers instead.  Call these only where
+// every lane of the wavefront is active (never inside a divergent branch).
+// bound_ctrl set: the lane shifted in from outside the wavefront reads 0, so
+// the instruction needs no prior value of its destination.
+__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ float from_left(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
+__device__ __forceinline__ float from_right(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
+__device__ __forceinline__ double from_left(double v)
+{
+    return __hiloint2double(dpp_shr1(__double2hiint(v)), dpp_shr1(__double2loint(v)));
+}
+__device__ __forceinline__ double from_right(double v)
+{
+    return __hiloint2double(dpp_shl1(__double2hiint(v)), dpp_shl1(__double2loint(v)));
+}
+
+// The same shifts with the value lane 0 (from_left_or) or lane 63
+// (from_right_or) receives from outside the wavefront given as `edge`
+// (bound_ctrl clear: a lane without a source lane keeps the old value).
+__device__ __forceinline__ int dpp_shr1_or(int edge, int v)
+{
+    return __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_shl1_or(int edge, int v)
+{
+    return __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float from_left_or(float edge, float v)
+{
+    return __int_as_float(dpp_shr1_or(__float_as_int(edge), __float_as_int(v)));
+}
+__device__ __forceinline__ float from_right_or(float edge, float v)
+{
+    return __int_as_float(dpp_shl1_or(__float_as_int(edge), __float_as_int(v)));
+}
+__device__ __forceinline__ double from_left_or(double edge, double v)
+{
+    return __hiloint2double(dpp_shr1_or(__double2hiint(edge), __double2hiint(v)),
+                            dpp_shr1_or(__double2loint(edge), __double2loint(v)));
+}
+__device__ __forceinline__ double from_right_or(double edge, double v)
+{
+    return __hiloint2double(dpp_shl1_or(__double2hiint(edge), __double2hiint(v)),
+                            dpp_shl1_or(__double2loint(edge), __double2loint(v)));
+}
+
+// The step kernel reads the solve description through the constant address
+// space: it is never written while a step runs, so the loads are scalar.  The
+// kernel parameter stays a plain pointer (host and device must see the same
+// kernel signature) and is cast inside device code.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) SolveDesc *DescPtr;
+#else
+typedef const SolveDesc *DescPtr;
+#endif
+
+// The two f and lambda buffers of one step (they swap every step).
+struct StepBufs {
+    const void *f_in;
+    void *f_out;
+    const double *lam_in;
+    double *lam_out;
+};
+
+// Raw buffer access to the f and lambda arrays: the lane's column offset is a
+// loop-invariant VGPR, the row and velocity-plane offsets a scalar register
+// (arrays stay below 4 GiB, which create() checks).
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)0xFFFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ void bload(float &v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    v = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ __forceinline__ void bload(double &v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    const i32x2 t = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    v = __hiloint2double(t.y, t.x);
+}
+// Stores are non-temporal (cache policy nt): the new state is not read again
+// in this step, and keeping it out of the caches leaves them to the lines
+// the adjacent strips and row blocks read twice (halo columns, block
+// boundary rows).
+constexpr int STORE_NT = 2;
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, vo, so, STORE_NT);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    i32x2 t;
+    t.x = __double2loint(v);
+    t.y = __double2hiint(v);
+    __builtin_amdgcn_raw_buffer_store_b64(t, r, vo, so, STORE_NT);
+}
+// Both members of a pair of opposite directions (see elem_of): one 8-byte
+// (float32) or 16-byte (float64) access per lane.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void bload2(float &a, float &b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    const i32x2 t = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    a = __int_as_float(t.x);
+    b = __int_as_float(t.y);
+}
+__device__ __forceinline__ void bload2(double &a, double &b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    const i32x4 t = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+    a = __hiloint2double(t.y, t.x);
+    b = __hiloint2double(t.w, t.z);
+}
+__device__ __forceinline__ void bstore2(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    i32x2 t;
+    t.x = __float_as_int(a);
+    t.y = __float_as_int(b);
+    __builtin_amdgcn_raw_buffer_store_b64(t, r, vo, so, STORE_NT);
+}
+__device__ __forceinline__ void bstore2(double a, double b, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+{
+    i32x4 t;
+    t.x = __double2loint(a);
+    t.y = __double2hiint(a);
+    t.z = __double2loint(b);
+    t.w = __double2hiint(b);
+    __builtin_amdgcn_raw_buffer_store_b128(t, r, vo, so, STORE_NT);
+}
+
+// Keeps a scalar offset opaque to the optimiser, so that the 33 plane offsets
+// are re-derived by one scalar add each instead of being hoisted out of the
+// row loop (where they would not fit in scalar registers).
+__device__ __forceinline__ uint32_t opaque(uint32_t x)
+{
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+// A wavefront owns a strip of 64 consecutive theta columns, one per lane, and
+// marches outward (or inward) over a block of rows.  The row being computed
+// and the next two in marching order are held in registers, the row behind
+// in a lane-private LDS slot: radial neighbours come from there, azimuthal
+// ones from the adjacent lanes, so each f value is read from memory once per
+// step (plus the two rows bounding the block).  The azimuthal neighbours of
+// lanes 0 and 63 (the halo columns, owned by the adjacent strips) come from
+// three gathered loads per row, lane q of which fetches one (plane, side)
+// pair, and are moved into lane 0 or 63 by readlane.  Strips start on
+// 64-column boundaries and rows are padded to a multiple of 64, so every
+// store of a plane or pair covers whole cache lines; lanes past the last
+// column own a padding column.  The second row ahead is requested a whole row
+// of compute before it is first needed.
+template <typename real, bool ROT>
+struct Strip {
+    DescPtr dp;
+    __amdgpu_buffer_rsrc_t fin, fout, lin, lout;
+    uint32_t vo, vo2, vol;   // byte offsets of this lane's column: rest plane, pair, lambda
+    uint32_t vos, vos2, vols;  // ... of the lane's own column (the padding for periodic images)
+    uint32_t vh1, vh2, vhl;  // byte offsets of this lane's halo gathers (plane and column)
+    uint32_t row_bytes, lrow_bytes, rest_bytes, pair_bytes;
+    uint32_t poff[4];     // rotated sectors: byte offset of the pair holding this lane's directions dd, dd + 4
+    bool pswap[4];        // ... and whether its members come in the other order
+    int lane, pc, rot;    // physical column, direction shift of this lane's data
+    bool useful;
+
+    // memory plane of velocity q for data whose direction index is shifted by r
+    static __device__ __forceinline__ int plane_of(int q, int r)
+    {
+        return q == 0 ? 0 : 1 + 8 * ((q - 1) / 8) + ((((q - 1) % 8) + r) & 7);
+    }
+
+    __device__ __forceinline__ Strip(DescPtr dp_, const StepBufs &b, int strip) : dp(dp_)
+    {
+        fin = rsrc_of(b.f_in);
+        fout = rsrc_of(b.f_out);
+        lin = rsrc_of(b.lam_in);
+        lout = rsrc_of(b.lam_out);
+        const int nt = dp->nt, sec = dp->sector;
+        lane = threadIdx.x & 63;
+        const int c0 = strip * STRIP;
+        const int col = c0 + lane;
+        // lanes past the last column hold periodic images of the first ones
+        const int wraps = col / nt;
+        pc = col - wraps * nt;
+        rot = ROT ? ((-wraps * sec) & 7) : 0;
+        useful = col < nt;
+        vo = (uint32_t)pc * (uint32_t)sizeof(real);
+        vo2 = 2u * vo;
+        vol = (uint32_t)pc * 8u;
+        vos = (uint32_t)col * (uint32_t)sizeof(real);
+        vos2 = 2u * vos;
+        vols = (uint32_t)col * 8u;
+        row_bytes = (uint32_t)dp->rstride * (uint32_t)sizeof(real);
+        lrow_bytes = (uint32_t)dp->pitch * 8u;
+        rest_bytes = (uint32_t)dp->plane * (uint32_t)sizeof(real);
+        pair_bytes = 2u * rest_bytes;
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            // direction dd of this lane's data is direction (dd + rot) % 8
+            poff[dd] = vo2 + rest_bytes + (uint32_t)((dd + rot) & 3) * pair_bytes;
+            pswap[dd] = ((dd + rot) & 4) != 0;
+        }
+        // halo columns: c0 - 1 (0 <= c0 < nt) and c0 + 64, as periodic images
+        const int cl = c0 == 0 ? nt - 1 : c0 - 1;
+        const int rl = ROT && c0 == 0 ? (sec & 7) : 0;
+        const int wr = (c0 + STRIP) / nt;
+        const int cr = c0 + STRIP - wr * nt;
+        const int rr = ROT ? ((-wr * sec) & 7) : 0;
+        // gather 1: lanes 0..32 left halo of planes 0..32, lanes 33..63 right
+        // halo of planes 0..30; gather 2: lanes 0, 1 right halo of planes 31,
+        // 32; lambda gather: lane 0 left, lane 1 right (other lanes repeat a
+        // valid address)
+        const int es = (int)sizeof(real);
+        const int64_t pt = dp->pitch;
+        vh1 = lane <= 32 ? (uint32_t)elem_of(plane_of(lane, rl), cl, pt) * es
+                         : (uint32_t)elem_of(plane_of(lane - 33, rr), cr, pt) * es;
+        vh2 = lane < 2 ? (uint32_t)elem_of(plane_of(31 + lane, rr), cr, pt) * es : (uint32_t)cl * es;
+        vhl = lane == 1 ? (uint32_t)cr * 8u : (uint32_t)cl * 8u;
+    }
+
+    __device__ __forceinline__ void load_row(int row, real f[NQ], double &lam) const
+    {
+        uint32_t so = (uint32_t)row * row_bytes;
+        bload(f[0], fin, vo, so);
+        if (ROT) {
+            // this lane's data of direction dir lives in direction (dir + rot) % 8
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t sk = so + (uint32_t)k * 4u * pair_bytes;
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd) {
+                    real a, b;
+                    bload2(a, b, fin, poff[dd], sk);
+                    f[1 + 8 * k + dd] = pswap[dd] ? b : a;
+                    f[5 + 8 * k + dd] = pswap[dd] ? a : b;
+                }
+            }
+        } else {
+            so = opaque(so + rest_bytes);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                bload2(f[1 + 8 * (c >> 2) + (c & 3)], f[5 + 8 * (c >> 2) + (c & 3)], fin, vo2, so);
+                so = opaque(so + pair_bytes);
+            }
+        }
+        bload(lam, lin, vol, (uint32_t)row * lrow_bytes);
+    }
+
+    // The halo values of row `row`: h[0], h[1] for f, h[2] for lambda.
+    __device__ __forceinline__ void load_halo(int row, real h[2], double &hl) const
+    {
+        const uint32_t so = (uint32_t)row * row_bytes;
+        bload(h[0], fin, vh1, so);
+        bload(h[1], fin, vh2, so);
+        bload(hl, lin, vhl, (uint32_t)row * lrow_bytes);
+    }
+};
+
+// Wave-uniform copy of lane l of v.
+__device__ __forceinline__ float lane_value(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// Halo of plane q from the two f gathers: left neighbour of lane 0, right
+// neighbour of lane 63.
+template <typename real>
+__device__ __forceinline__ real halo_left(const real h[2], int q)
+{
+    return lane_value(h[0], q);
+}
+template <typename real>
+__device__ __forceinline__ real halo_right(const real h[2], int q)
+{
+    return q <= 30 ? lane_value(h[0], 33 + q) : lane_value(h[1], q - 31);
+}
+
+// Per-cell quantities of one update (Sec. II.B-C): moments, F_k(T), the f^eq
+// polynomial and the BGK / chemical factors (the Cochran rate gated by the
+// ignition temperature, in float64; M dt = f^eq beta (|v - u|^2 - 2T) with
+// beta = Q R dt / (2 T^2), D = 2).
+template <typename real>
+struct Cell {
+    real rho, e, ux, uy, u2, T, beta, omega, keep, Bz;
+    double Td, a, b;
+    bool on;
+    real F[5];
+    EqPoly<real> EP;
+
+    Cell() = default;
+    __device__ __forceinline__ Cell(DescPtr dp, const real x[NQ], double lc)
+    {
+        real jx, jy;
+        raw_moments(x, rho, jx, jy, e);
+        init_moments(dp, jx, jy, lc);
+    }
+    // from rho, e (members) and the momentum jx, jy
+    __device__ __forceinline__ void init_moments(DescPtr dp, real jx, real jy, double lc)
+    {
+        const real irho = (real)1 / rho;
+        ux = jx * irho;
+        uy = jy * irho;
+        u2 = ux * ux + uy * uy;
+        T = e * irho - (real)0.5 * u2;
+        Td = (double)T;
+        weights(dp->A, Td, F);
+        EP = EqPoly<real>(ux, uy, u2, T);
+        a = 0.0;
+        b = 0.0;
+        double R = 0.0;
+        on = dp->reacts && Td > dp->T_th;
+        if (on) {
+            const double p = (double)rho * Td;
+            a = dp->w1 * ipow(p, dp->m);
+            b = dp->w2 * ipow(p, dp->n);
+            R = (1.0 - lc) * (a + b * lc);
+        }
+        beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
+        omega = (real)dp->omega;
+        keep = (real)1 - omega;
+        Bz = (real)-2 * beta * T;
+    }
+    // the rest particle after collision (it does not stream)
+    __device__ __forceinline__ real rest(real x0) const
+    {
+        return rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * x0;
+    }
+    // lambda after the closed-form Cochran step
+    __device__ __forceinline__ double reacted(DescPtr dp, double lc) const
+    {
+        if (on && a + b > 0.0) {
+            const double q1 = (1.0 - lc) * exp(-(a + b) * dp->dt);
+            return 1.0 - (a + b) * q1 / ((a + b * lc) + b * q1);
+        }
+        return lc;
+    }
+};
+
+// Row `row` of the strip into f, or a ghost row outside [0, nr): below r_min
+// the zero-gradient copy of row 0 or the disc-centre rule f(-1, j, k, i) =
+// f(0, j, k, (i+4)%8) (Sec. II.D); above r_max the zero-gradient copy of row
+// nr-1.  `edge` holds the boundary row the ghost copies.
+template <typename real, bool ROT>
+__device__ __forceinline__ void row_or_ghost(const Strip<real, ROT> &S, int row, real f[NQ], double &lam,
+                                             const real edge[NQ], double ledge)
+{
+    if (row >= 0 && row < S.dp->nr) {
+        S.load_row(row, f, lam);
+        return;
+    }
+    const bool disc = row < 0 && S.dp->disc;
+    f[0] = edge[0];
+#pragma unroll
+    for (int q = 1; q < NQ; ++q) {
+        const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8;
+        f[q] = disc ? edge[base + ((dir + 4) & 7)] : edge[q];
+    }
+    lam = ledge;
+}
+
+// Whether step `s` of a solve makes a drift record.
+__device__ __forceinline__ bool records(DescPtr dp, int64_t s)
+{
+    return dp->diag_every > 0 && s >= dp->state->rec_from && s % dp->diag_every == 0;
+}
+
+}  // namespace
+}  // namespace pdbm

@@ -69,7 +69,7 @@ struct DiagCtl {
     int32_t pad;
 };
 
-// Kernel launchers (pdbm_kernels.hip).  All enqueue on `st` and return the
+// Kernel launchers (pdbm_step.hip, pdbm_step2.hip, pdbm_cells.hip).  All enqueue on `st` and return the
 // hipError_t of the launch.
 //
 // One step of every solve listed: `descs` is a device array of solve

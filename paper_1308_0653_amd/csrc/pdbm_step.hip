@@ -1,0 +1,474 @@
+// One time step per launch (k_step): every solve of the launch, float64 or
+// float32, full annulus or rotated sector, wavefront strips of 64 theta
+// columns or, for a single column, wavefronts of 64 rows; and the kernels
+// that add up the drift records (k_records) and move packed solves' step
+// bases on (k_advance).
+#include "pdbm_device.h"
+
+namespace pdbm {
+namespace {
+
+// One row of one strip: moments, F_k(T), f^eq, BGK + chemical term, Cochran
+// lambda, donor-cell fluxes of f and lambda.  fc: row i.  Marching outward
+// (down = false): prev (LDS, this lane's column) holds row i-1 and fn row
+// i+1; marching inward the roles swap.  prev is replaced by row i as it is
+// consumed.  mr[dd] / mt[dd]: which side is upwind for direction dd (its
+// opposite dd+4 takes the other side).
+template <typename real, bool ROT>
+__device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, real (*prev)[64], const real fc[NQ],
+                                           const real fn[NQ], const real hf[2], double hlam, double lbehind,
+                                           double lc, double lahead,
+                                           const bool mr[4], const bool mt[4], const real acr[4], const real ctv[4],
+                                           bool lr_behind, double csx, double csy, double red[5], bool diag)
+{
+    const DescPtr dp = S.dp;
+    // (1)-(3) moments, weights, f^eq polynomial, BGK and chemical factors
+    const Cell<real> C(dp, fc, lc);
+    const real rho = C.rho, e = C.e, ux = C.ux, uy = C.uy, u2 = C.u2, T = C.T;
+    const real beta = C.beta, omega = C.omega, keep = C.keep, Bz = C.Bz;
+    const double Td = C.Td;
+    const real *F = C.F;
+    const EqPoly<real> &EP = C.EP;
+
+    // azimuthal Courant magnitudes of this row (the geometric 1/r term)
+    const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
+    const real kt = (real)(dp->dt_dth / ri);
+    real act[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) act[dd] = fabs(ctv[dd]) * kt;
+
+    const bool store = S.useful;
+    const int lane = S.lane;
+    // pair c of this row sits at rowoff + rest plane + c * pb (pb re-derived
+    // per row so the 16 products stay scalar arithmetic inside the loop)
+    const uint32_t rowoff = (uint32_t)ir * S.row_bytes;
+    const uint32_t pb = opaque(S.pair_bytes);
+    const uint32_t pairs = rowoff + S.rest_bytes;
+
+    // rest particle: no streaming
+    // every lane stores, periodic images into their own column of the row
+    // padding (see stage_row)
+    const real rest = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * fc[0];
+    bstore(rest, S.fout, S.vos, rowoff);
+
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real v = (real)speed(k);
+        const real rF = rho * F[k];
+        const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
+        const int base = 1 + 8 * (k - 1);
+        // the ring's new values, stored together under one lane mask (in
+        // halves where the rotated sector's per-lane plane offsets already
+        // hold registers)
+        constexpr int G = ROT ? 2 : 4;  // directions dd per store group
+        real o[8];
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            const real z = v * EP.w(dd);
+            real pp, pm;
+            EP.eval(z, pp, pm);
+            const real bz = Bz * z;
+#pragma unroll
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const int q = base + dd + 4 * sgn;
+                const real x = fc[q];
+                const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * x : rF * pm * (Ak - bz) + omega * x;
+                // upwind neighbours: C >= 0 takes the lower one (Sec. II.C)
+                const real behind = prev[q][lane];
+                prev[q][lane] = x;
+                const bool rb = sgn == 0 ? mr[dd] : !mr[dd];
+                const real nbr = rb ? behind : fn[q];
+                // both shifts and both halo values are taken by every lane
+                // (a DPP read of a lane switched off by a branch would return
+                // 0), then selected; lanes 0 and 63 take the halo columns
+                const real sl = from_left(x), sr = from_right(x);
+                const real hl = halo_left(hf, q), hr = halo_right(hf, q);
+                const real left = lane == 0 ? hl : sl;
+                const real right = lane == 63 ? hr : sr;
+                const bool tl = sgn == 0 ? mt[dd] : !mt[dd];
+                const real nbt = tl ? left : right;
+                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+            }
+            // lanes holding rotated sector images store into the padding
+            // too (their values are never read)
+            if (dd % G == G - 1) {
+#pragma unroll
+                for (int e = dd + 1 - G; e <= dd; ++e)
+                    bstore2(o[e], o[e + 4], S.fout, S.vos2, pairs + (uint32_t)(4 * (k - 1) + e) * pb);
+            }
+        }
+    }
+
+    // (4) lambda: closed-form Cochran step, then upwind by own-cell u
+    const double uxd = (double)ux, uyd = (double)uy;
+    const double urp = uxd * csx + uyd * csy;
+    const double utp = -uxd * csy + uyd * csx;
+    const double lreac = C.reacted(dp, lc);
+    const double sll = from_left(lc), slr = from_right(lc);
+    const double hll = lane_value(hlam, 0), hlr = lane_value(hlam, 1);
+    const double lleft = lane == 0 ? hll : sll;
+    const double lright = lane == 63 ? hlr : slr;
+    const double lr = (urp >= 0.0) == lr_behind ? lbehind : lahead;
+    const double lt = utp >= 0.0 ? lleft : lright;
+    const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
+    bstore(lnew, S.lout, S.vols, (uint32_t)ir * S.lrow_bytes);
+
+    if (diag && store) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lc, ri * dp->dr * dp->dth, dp->Q);
+}
+
+// Work of one wavefront: strip `strip`, rows [i0, i1), marched outward or,
+// with `down`, inward.  prev: this wavefront's [NQ][64] LDS slots.
+template <typename real, bool ROT>
+__device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
+                                      real (*prev)[64], double red[5], bool diag)
+{
+    const Strip<real, ROT> S(dp, bufs, strip);
+    const int lane = S.lane;
+    const double2 cs = dp->cs[S.pc];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    // polar components of directions dd = 0..3 at theta_j (dd+4 is the negative):
+    // v_r = v (cos(dd pi/4) cos th + sin(dd pi/4) sin th),
+    // v_theta = v (sin(dd pi/4) cos th - cos(dd pi/4) sin th)
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    const real kr = (real)dp->dt_dr;
+    real acr[4];
+    bool mr[4], mt[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        acr[dd] = fabs(crv[dd]) * kr;
+        mr[dd] = (crv[dd] >= (real)0) != down;  // true: the upwind radial neighbour is the row behind
+        mt[dd] = ctv[dd] >= (real)0;            // true: the upwind azimuthal neighbour is lane-1
+    }
+    const int step = down ? -1 : 1;
+    const int first = down ? i1 - 1 : i0;
+    const int count = i1 - i0;
+    // halos of a row are gathered right after its main loads, when the
+    // adjacent strips fetch the same lines (they then hit in L2)
+    real fc[NQ], fn[NQ], fnn[NQ], hc[2], hn[2], hnn[2];
+    double lp, lc, ln, lnn, hlc, hln, hlnn;
+    S.load_row(first, fc, lc);
+    S.load_halo(first, hc, hlc);
+    row_or_ghost(S, first + step, fn, ln, fc, lc);
+    if (count > 1) S.load_halo(first + step, hn, hln);
+    row_or_ghost(S, first - step, fnn, lp, fc, lc);  // the row behind the first
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) prev[q][lane] = fnn[q];
+    int ir = first;
+    for (int n = 0; n < count; ++n, ir += step) {
+        // the second row ahead is the radial neighbour of the next row
+        // computed, if there is one; rows computed are never ghosts
+        if (n + 1 < count) row_or_ghost(S, ir + 2 * step, fnn, lnn, fn, ln);
+        if (n + 2 < count) S.load_halo(ir + 2 * step, hnn, hlnn);
+        update_row<real, ROT>(S, ir, prev, fc, fn, hc, hlc, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, red,
+                              diag);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            fc[q] = fn[q];
+            fn[q] = fnn[q];
+        }
+        hc[0] = hn[0];
+        hc[1] = hn[1];
+        hlc = hln;
+        hn[0] = hnn[0];
+        hn[1] = hnn[1];
+        hln = hlnn;
+        lp = lc;
+        lc = ln;
+        ln = lnn;
+        // Compiler-only barrier: the LDS slots must not be promoted to
+        // registers across iterations (they exist to free those registers).
+        asm volatile("" ::: "memory");
+    }
+}
+
+// Memory plane of velocity q whose direction index is shifted by r.
+__device__ __forceinline__ int shifted_plane(int q, int r)
+{
+    return q == 0 ? 0 : 1 + 8 * ((q - 1) / 8) + ((((q - 1) % 8) + r) & 7);
+}
+
+// One step of 64 consecutive rows of a solve with a single theta column
+// (ntheta = 1, the quasi-one-dimensional runs of Sec. III): lane l owns row
+// 64 blk + l.  Radial neighbours come from the adjacent lanes (DPP shifts)
+// and, for lanes 0 and 63, from gathers of the rows below and above the
+// block, which apply the radial ghost rules of Sec. II.D.  The azimuthal
+// neighbours of a cell are the cell itself with directions turned by the
+// sector (periodic halo, f_{k,i}(j-1) = f_{k,(i+s)%8}(j) and f_{k,i}(j+1) =
+// f_{k,(i-s)%8}(j)); they are read back from the wavefront's LDS slot.
+// The arithmetic per cell is that of update_row.
+template <typename real>
+__device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, int blk, real (*slot)[64],
+                                             double red[5], bool diag)
+{
+    const int lane = threadIdx.x & 63;
+    const int nr = dp->nr, sec = dp->sector;
+    const int r0 = blk * 64;
+    const int row = r0 + lane;
+    const int re = min(row, nr - 1);  // lanes past the last row hold its zero-gradient image
+    const bool store = row < nr;
+    const __amdgpu_buffer_rsrc_t fin = rsrc_of(bufs.f_in), fout = rsrc_of(bufs.f_out);
+    const __amdgpu_buffer_rsrc_t lin = rsrc_of(bufs.lam_in), lout = rsrc_of(bufs.lam_out);
+    const uint32_t es = (uint32_t)sizeof(real);
+    const uint32_t rowb = (uint32_t)dp->rstride * es;
+    const uint32_t rb = (uint32_t)dp->plane * es, pb = 2u * rb;  // rest plane, one pair (column 0)
+    const int64_t pt = dp->pitch;
+    const uint32_t lrowb = (uint32_t)dp->pitch * 8u;
+    const uint32_t vo = (uint32_t)re * rowb, vol = (uint32_t)re * lrowb;
+
+    real fc[NQ];
+    double lc;
+    bload(fc[0], fin, vo, 0u);
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+        bload2(fc[1 + 8 * (c >> 2) + (c & 3)], fc[5 + 8 * (c >> 2) + (c & 3)], fin, vo, rb + (uint32_t)c * pb);
+    bload(lc, lin, vol, 0u);
+    // gathers of the row below the block (ghost of row 0 at r_min: a copy,
+    // or at the disc centre row 0 with directions turned by 4) and of the
+    // row above it (clamped: the zero-gradient copy of the last row)
+    const int rlo = r0 == 0 ? 0 : r0 - 1;
+    const int tlo = r0 == 0 && dp->disc ? 4 : 0;
+    const int rhi = min(r0 + 64, nr - 1);
+    const uint32_t vh1 = lane <= 32 ? (uint32_t)rlo * rowb + (uint32_t)elem_of(shifted_plane(lane, tlo), 0, pt) * es
+                                    : (uint32_t)rhi * rowb + (uint32_t)elem_of(lane - 33, 0, pt) * es;
+    const uint32_t vh2 = lane < 2 ? (uint32_t)rhi * rowb + (uint32_t)elem_of(31 + lane, 0, pt) * es
+                                  : (uint32_t)rlo * rowb;
+    const uint32_t vhl = lane == 1 ? (uint32_t)rhi * lrowb : (uint32_t)rlo * lrowb;
+    real hf[2];
+    double hlam;
+    bload(hf[0], fin, vh1, 0u);
+    bload(hf[1], fin, vh2, 0u);
+    bload(hlam, lin, vhl, 0u);
+
+    // (1)-(3) moments, weights, f^eq polynomial, BGK and chemical factors
+    const Cell<real> C(dp, fc, lc);
+    const real rho = C.rho, e = C.e, ux = C.ux, uy = C.uy, u2 = C.u2, T = C.T;
+    const real beta = C.beta, omega = C.omega, keep = C.keep, Bz = C.Bz;
+    const double Td = C.Td;
+    const real *F = C.F;
+    const EqPoly<real> &EP = C.EP;
+
+    // polar components of directions dd = 0..3 at theta_0 (dd+4 is the negative)
+    const double2 cs = dp->cs[0];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    const double ri = dp->r_min + ((double)re + 0.5) * dp->dr;
+    const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
+    real acr[4], act[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        acr[dd] = fabs(crv[dd]) * kr;
+        act[dd] = fabs(ctv[dd]) * kt;
+    }
+    // the cell's distributions, for its rotated azimuthal neighbours
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) slot[q][lane] = fc[q];
+
+    const real rest = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * fc[0];
+    if (store) bstore(rest, fout, vo, 0u);
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real v = (real)speed(k);
+        const real rF = rho * F[k];
+        const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
+        const int base = 1 + 8 * (k - 1);
+        real o[8];
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            const real z = v * EP.w(dd);
+            real pp, pm;
+            EP.eval(z, pp, pm);
+            const real bz = Bz * z;
+#pragma unroll
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const int q = base + dd + 4 * sgn;
+                const real x = fc[q];
+                const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * x : rF * pm * (Ak - bz) + omega * x;
+                // radial upwind (C_r >= 0 takes the row below); every lane
+                // takes both shifts, then selects
+                const real sl = from_left(x), sr = from_right(x);
+                const real hl = halo_left(hf, q), hr = halo_right(hf, q);
+                const real lower = lane == 0 ? hl : sl;
+                const real upper = lane == 63 ? hr : sr;
+                const bool below = sgn == 0 ? crv[dd] >= (real)0 : crv[dd] < (real)0;
+                const real nbr = below ? lower : upper;
+                // azimuthal upwind (C_theta >= 0 takes j-1): this cell with
+                // the direction index turned by +s (j-1) or -s (j+1)
+                const bool left = sgn == 0 ? ctv[dd] >= (real)0 : ctv[dd] < (real)0;
+                const int dir = dd + 4 * sgn;
+                const real nbt = slot[base + ((dir + (left ? sec : 8 - sec)) & 7)][lane];
+                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+            }
+        }
+        if (store) {
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd) bstore2(o[dd], o[dd + 4], fout, vo, rb + (uint32_t)(4 * (k - 1) + dd) * pb);
+        }
+    }
+
+    // (4) lambda: closed-form Cochran step, then upwind by own-cell u (the
+    // azimuthal neighbour of the single column is the cell itself)
+    const double uxd = (double)ux, uyd = (double)uy;
+    const double urp = uxd * cs.x + uyd * cs.y;
+    const double lreac = C.reacted(dp, lc);
+    const double sll = from_left(lc), slr = from_right(lc);
+    const double hll = lane_value(hlam, 0), hlr = lane_value(hlam, 1);
+    const double llow = lane == 0 ? hll : sll;
+    const double lup = lane == 63 ? hlr : slr;
+    const double lr = urp >= 0.0 ? llow : lup;
+    const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr);
+    if (store) bstore(lnew, lout, vol, 0u);
+
+    if (diag && store) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lc, ri * dp->dr * dp->dth, dp->Q);
+}
+
+// Occupancy: float32 rows fit two wavefronts per SIMD; float64 rows take
+// the whole register file of one (the next row in flight is 66 VGPRs).
+template <typename real>
+struct StepOcc {
+    static constexpr int waves = sizeof(real) == 4 ? 2 : 1;
+};
+
+// One time step of every solve of the launch.  Wavefront w of the grid takes
+// tile t = (its block's XCD-ordered index) * 4 + w, which the tile table maps
+// to (solve, tile of that solve); a solve's tile lt is row block lt / nstrip,
+// strip lt % nstrip.  Each wavefront works on its own: no barriers and no
+// atomics.  A drift-report step leaves per-wavefront partial sums in its
+// slot of the solve's partial-sum ring; k_records adds them up later.
+template <typename real, bool ROT>
+__global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const SolveDesc *descs, const uint2 *tiles,
+                                                                       int ntiles, const int64_t *bases,
+                                                                       int64_t step_off, int flip)
+{
+    const int nb = gridDim.x;
+    const int blk = xcd_tile(blockIdx.x, nb);
+    // wave-uniform by construction; tell the compiler so that the row loop
+    // and the offsets derived from it live in scalar registers
+    const int t = __builtin_amdgcn_readfirstlane(blk * (BLOCK / 64) + (threadIdx.x >> 6));
+    if (t >= ntiles) return;
+    int solve = 0, lt = t;
+    if (tiles) {
+        const uint2 e = tiles[t];
+        solve = __builtin_amdgcn_readfirstlane((int)e.x);
+        lt = __builtin_amdgcn_readfirstlane((int)e.y);
+    }
+    const DescPtr dp = (DescPtr)(descs + solve);
+    const int64_t step = (bases ? bases[solve] : 0) + step_off;
+    if (step >= dp->nsteps) return;
+    const bool diag = records(dp, step);
+    const int cur = (int)((step + flip) & 1);
+    const StepBufs bufs{dp->f[cur], dp->f[cur ^ 1], dp->lam[cur], dp->lam[cur ^ 1]};
+    __shared__ real prev[BLOCK / 64][NQ][64];
+    double red[5] = {0, 0, 0, 0, 0};
+    // row-block major: the strips of one row block sit side by side in the
+    // same XCD and share their halo columns in its L2; odd row blocks march
+    // inward so that the rows bounding two blocks are read by both at once.
+    if (dp->nt == 1) {
+        // one theta column: lanes along r
+        radial_block<real>(dp, bufs, lt, prev[threadIdx.x >> 6], red, diag);
+    } else {
+        const int rows = dp->rows, nstrip = dp->nstrip;
+        const int rb = lt / nstrip, strip = lt - rb * nstrip;
+        const int i0 = rb * rows;
+        const int i1 = min(i0 + rows, dp->nr);
+        march<real, ROT>(dp, bufs, strip, i0, i1, (rb & 1) != 0, prev[threadIdx.x >> 6], red, diag);
+    }
+    if (diag) {
+        const int64_t slot = (step / dp->diag_every) % PART_RING;
+        double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double v = wave_sum(red[i]);
+            if ((threadIdx.x & 63) == 0) part[i] = v;
+        }
+    }
+}
+
+__global__ void k_advance(int64_t *bases, int n, int64_t by)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) bases[i] += by;
+}
+
+// Drift records of the steps [base + lo, base + hi) of each solve, where base
+// is bases[solve] (0 without bases): block (solve, r) adds up the partial sums
+// of the r-th record in that range, one wavefront, in a fixed order, so the
+// record does not depend on the order in which wavefronts finished.
+__global__ __launch_bounds__(64) void k_records(const SolveDesc *descs, const int64_t *bases, int64_t lo, int64_t hi)
+{
+    const DescPtr dp = (DescPtr)(descs + blockIdx.x);
+    const int64_t de = dp->diag_every;
+    if (de <= 0) return;
+    const int64_t base = bases ? bases[blockIdx.x] : 0;
+    const int64_t s0 = max(base + lo, dp->state->rec_from);
+    const int64_t s1 = min(base + hi, dp->nsteps);
+    const int64_t k = (s0 + de - 1) / de + blockIdx.y;  // record k is step k * de
+    if (s0 >= s1 || k * de >= s1) return;
+    const int lane = threadIdx.x;
+    const double *part = dp->wpart + (size_t)(k % PART_RING) * dp->nwaves * 5;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int w = lane; w < dp->nwaves; w += 64)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i] += part[5 * (size_t)w + i];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) acc[i] = wave_sum(acc[i]);
+    if (lane == 0) {
+        pdbm_diag r;
+        r.step = k * de;
+        r.mass = acc[0];
+        r.energy = acc[1];
+        r.chem = acc[2];
+        r.n_nonfinite = (int64_t)acc[3];
+        r.n_nonphys = (int64_t)acc[4];
+        dp->hist[k % HIST_CAP] = r;
+    }
+}
+
+}  // namespace
+
+int solve_waves(int nr, int nt, int rows)
+{
+    if (nt == 1) return (nr + STRIP - 1) / STRIP;  // lanes along r: 64 rows per wavefront
+    return (int)((int64_t)((nr + rows - 1) / rows) * ((nt + STRIP - 1) / STRIP));
+}
+
+hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
+                       int flip, bool fp32, bool rot, hipStream_t st)
+{
+    const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
+    if (nb == 0) return hipSuccess;
+    if (fp32) {
+        if (rot)
+            hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flip);
+        else
+            hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flip);
+    } else {
+        if (rot)
+            hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flip);
+        else
+            hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flip);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(int64_t *bases, int n, int64_t by, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, st, bases, n, by);
+    return hipGetLastError();
+}
+
+hipError_t launch_records(const SolveDesc *descs, int n, const int64_t *bases, int64_t lo, int64_t hi, hipStream_t st)
+{
+    if (n <= 0 || hi <= lo) return hipSuccess;
+    const int nrec = (int)std::min<int64_t>(hi - lo, PART_RING);
+    hipLaunchKernelGGL(k_records, dim3(n, nrec), dim3(64), 0, st, descs, bases, lo, hi);
+    return hipGetLastError();
+}
+
+}  // namespace pdbm

@@ -1,0 +1,528 @@
+// Two time steps per launch, in one pass over f (k_step2): float64 solves
+// of the full annulus with more than one theta column.
+#include "pdbm_device.h"
+
+namespace pdbm {
+namespace {
+
+// ------------------------------------------------------ two steps per pass --
+// Steps s and s + 1 in one pass over f.  Stage A computes the state after
+// step s (g) one row ahead of stage B, which computes the state after step
+// s + 1 from g and stores it: g never leaves the wavefront.  Stage B's
+// azimuthal neighbours of lanes 0 and 63 are g at the columns bordering the
+// strip; the wavefront computes those cells itself at the start
+// (edge_cells), as the adjacent strips do in their own stage A.  A block of
+// R rows runs stage A on R + 2 rows and reads R + 4 rows of f, so each f
+// value is read about 1.3 times (block boundaries, edge-cell gathers) and
+// written once per two steps.
+
+// Azimuthal neighbours of lanes 0 and 63 for stage A: the three gathered
+// loads of a row of the input state, written to an LDS row and read back by
+// every lane (hb[q] left halo of plane q, hb[33 + q] right halo; hl[0], hl[1]
+// lambda).
+template <typename real>
+struct LdsHalo {
+    const real *hb;
+    const double *hl;
+    __device__ __forceinline__ real left(int q) const { return hb[q]; }
+    __device__ __forceinline__ real right(int q) const { return hb[33 + q]; }
+    __device__ __forceinline__ double lleft() const { return hl[0]; }
+    __device__ __forceinline__ double lright() const { return hl[1]; }
+};
+// The gathered halo registers of one row (see Strip::load_halo).
+template <typename real>
+struct GatherHalo {
+    real h[2];
+    double hl;
+};
+
+// ... and from the edge cells of the intermediate state in LDS (stage B).  Of
+// each pair of opposite directions an edge cell keeps only the one lane 0
+// (left side) or lane 63 (right side) takes from that side, in slot
+// 4 (k - 1) + (direction mod 4).
+template <typename real>
+struct EdgeHalo {
+    const real *L, *R;
+    double ll, lr;
+    static __device__ __forceinline__ int slot(int q) { return ((q - 1) >> 3) * 4 + ((q - 1) & 3); }
+    __device__ __forceinline__ real left(int q) const { return L[slot(q)]; }
+    __device__ __forceinline__ real right(int q) const { return R[slot(q)]; }
+    __device__ __forceinline__ double lleft() const { return ll; }
+    __device__ __forceinline__ double lright() const { return lr; }
+};
+
+// One row of one of the two steps: the arithmetic of update_row, with the
+// azimuthal halo from H.  Radial neighbours: the row behind in compact LDS
+// slots (of each opposite pair of directions only the one that takes its
+// upwind value from behind, slot 4 (k - 1) + (direction mod 4); replaced by
+// this row's as they are read), the row ahead in `fn` (stage A) or in the
+// full LDS row `ga` (stage B).  STAGEA: the new row goes to `ga` and `lout`,
+// for every lane (stage B reads the periodic images too); otherwise it is
+// stored, for the strip's own columns.
+template <typename real, bool STAGEA, class Halo>
+__device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, real (*behind)[64], const real fc[NQ],
+                                          const real *fn, real (*ga)[64], const Halo &H, double lbehind, double lc,
+                                          double lahead, const bool mr[4], const bool mt[4], const real acr[4],
+                                          const real ctv[4], bool lr_behind, double csx, double csy, double &lout,
+                                          double red[5], bool diag)
+{
+    const DescPtr dp = S.dp;
+    const Cell<real> C(dp, fc, lc);
+    const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
+    const real kt = (real)(dp->dt_dth / ri);
+    real act[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) act[dd] = fabs(ctv[dd]) * kt;
+
+    const bool store = S.useful;
+    const int lane = S.lane;
+    const uint32_t rowoff = (uint32_t)ir * S.row_bytes;
+    const uint32_t pb = opaque(S.pair_bytes);
+    const uint32_t pairs = rowoff + S.rest_bytes;
+
+    // stage B stores from every lane, periodic images into their own
+    // column of the row padding (nothing reads it): no store sits under a
+    // lane mask, which keeps the exec-mask branches and their registers out
+    // of the row loop
+    const real rest = C.rest(fc[0]);
+    if (STAGEA)
+        ga[0][lane] = rest;
+    else
+        bstore(rest, S.fout, S.vos, rowoff);
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+        const real v = (real)speed(k);
+        const real rF = C.rho * C.F[k];
+        const real Ak = C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T);
+        const int base = 1 + 8 * (k - 1);
+        real o[8];
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            const real z = v * C.EP.w(dd);
+            real pp, pm;
+            C.EP.eval(z, pp, pm);
+            const real bz = C.Bz * z;
+            const int c = 4 * (k - 1) + dd;
+            const real back = behind[c][lane];
+            behind[c][lane] = mr[dd] ? fc[base + dd] : fc[base + dd + 4];
+#pragma unroll
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                const int q = base + dd + 4 * sgn;
+                const real x = fc[q];
+                const real coll =
+                    sgn == 0 ? rF * pp * (Ak + bz) + C.omega * x : rF * pm * (Ak - bz) + C.omega * x;
+                const bool rb = sgn == 0 ? mr[dd] : !mr[dd];
+                real ahead;
+                if constexpr (STAGEA)
+                    ahead = fn[q];
+                else
+                    ahead = ga[q][lane];
+                const real nbr = rb ? back : ahead;
+                // every lane takes both shifts (lanes 0 and 63 the halo
+                // values), then selects
+                const real left = from_left_or(H.left(q), x);
+                const real right = from_right_or(H.right(q), x);
+                const bool tl = sgn == 0 ? mt[dd] : !mt[dd];
+                const real nbt = tl ? left : right;
+                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+            }
+        }
+        if (STAGEA) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) ga[base + i][lane] = o[i];
+        } else {
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd)
+                bstore2(o[dd], o[dd + 4], S.fout, S.vos2, pairs + (uint32_t)(4 * (k - 1) + dd) * pb);
+        }
+    }
+
+    const double uxd = (double)C.ux, uyd = (double)C.uy;
+    const double urp = uxd * csx + uyd * csy;
+    const double utp = -uxd * csy + uyd * csx;
+    const double lreac = C.reacted(dp, lc);
+    const double lleft = from_left_or(H.lleft(), lc);
+    const double lright = from_right_or(H.lright(), lc);
+    const double lr = (urp >= 0.0) == lr_behind ? lbehind : lahead;
+    const double lt = utp >= 0.0 ? lleft : lright;
+    const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
+    if (STAGEA)
+        lout = lnew;
+    else
+        bstore(lnew, S.lout, S.vols, (uint32_t)ir * S.lrow_bytes);
+
+    if (diag && store) diag_cell(red, (double)C.rho, uxd, uyd, C.Td, (double)C.e, lc, ri * dp->dr * dp->dth, dp->Q);
+}
+
+// The value the other lane of a lane pair (lanes 2m, 2m + 1) holds.
+__device__ __forceinline__ float pair_swap(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double pair_swap(double v)
+{
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xf, 0xf, false),
+                            __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xf, 0xf, false));
+}
+
+// The intermediate state at the columns bordering strip `strip`, c0 - 1
+// (left) and c0 + 64 (right) as periodic images, for the rows [i0, i1) of the
+// block.  Two lanes take one cell: lane 32 side + 2 e + h takes row i0 + e of
+// its side, h = 0 the speeds 1 and 2 (and the rest particle), h = 1 the
+// speeds 3 and 4.  Each lane gathers its pairs of the cell and of the cell's
+// upwind neighbours (radial ghost rules of Sec. II.D included), one access
+// per pair; the two lanes add up their partial moments, and each updates its
+// pairs as stage A of the strip owning the column does.  Of each opposite
+// pair of directions it keeps the one that lane 0 (left side) or lane 63
+// (right side) takes from there; the first lane of the two keeps lambda.
+// Every lane runs every instruction up to the final stores (the moment
+// exchange is a lane shift).
+template <typename real>
+__device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int strip, int i0, int i1,
+                                           real (*ef)[FUSE_ROWS][16], double (*el)[FUSE_ROWS])
+{
+    const DescPtr dp = S.dp;
+    const int lane = S.lane, side = lane >> 5, e = (lane >> 1) & 15, h = lane & 1;
+    const int count = i1 - i0;
+    const int nr = dp->nr, nt = dp->nt;
+    const int r = i0 + min(e, count - 1);  // lanes past the block repeat its last row
+    const int c0 = strip * STRIP;
+    const int pc = side == 0 ? (c0 + nt - 1) % nt : (c0 + STRIP) % nt;
+    const int pl = (pc + nt - 1) % nt, pr = (pc + 1) % nt;
+    const int pk = (side == 0 ? c0 : c0 + STRIP - 1) % nt;  // column of lane 0 / lane 63
+    const double2 cs = dp->cs[pc], ck = dp->cs[pk];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    const real kcth = (real)ck.x, ksth = (real)ck.y;
+    const real kctv[4] = {-ksth, (real)SQH * (kcth - ksth), kcth, (real)SQH * (kcth + ksth)};
+
+    const uint32_t es = (uint32_t)sizeof(real), rowb = S.row_bytes, lrowb = S.lrow_bytes;
+    // radial neighbours: below row 0 the copy of row 0 (disc centre: with
+    // directions turned by 4, i.e. the members of each pair swapped), above
+    // row nr - 1 the copy of row nr - 1
+    const int rlo = max(r - 1, 0), rhi = min(r + 1, nr - 1);
+    const bool turn = r == 0 && dp->disc;
+    const uint32_t orow = (uint32_t)r * rowb, olo = (uint32_t)rlo * rowb, ohi = (uint32_t)rhi * rowb;
+    const uint32_t cc = 2u * (uint32_t)pc * es, cl = 2u * (uint32_t)pl * es, cr = 2u * (uint32_t)pr * es;
+    // this lane's pairs 8 h .. 8 h + 7 (speeds 2 h + 1, 2 h + 2): directions
+    // dd of pair i in x[i], dd + 4 in x[i + 8]
+    real x[16], nbr[16], nbt[16], x0;
+    bload(x0, S.fin, orow + (uint32_t)pc * es, 0u);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t po = S.rest_bytes + (uint32_t)(8 * h + i) * S.pair_bytes;
+        const int dd = i & 3;
+        real lo0, lo1, hi0, hi1, l0, l1, r0, r1;
+        bload2(x[i], x[i + 8], S.fin, orow + cc + po, 0u);
+        bload2(lo0, lo1, S.fin, olo + cc + po, 0u);
+        bload2(hi0, hi1, S.fin, ohi + cc + po, 0u);
+        bload2(l0, l1, S.fin, orow + cl + po, 0u);
+        bload2(r0, r1, S.fin, orow + cr + po, 0u);
+        const real t0 = turn ? lo1 : lo0, t1 = turn ? lo0 : lo1;
+        const bool mr = crv[dd] >= (real)0, mt = ctv[dd] >= (real)0;
+        // direction dd takes the lower row if mr and the left column if mt,
+        // dd + 4 the other ones
+        nbr[i] = mr ? t0 : hi0;
+        nbr[i + 8] = mr ? hi1 : t1;
+        nbt[i] = mt ? l0 : r0;
+        nbt[i + 8] = mt ? r1 : l1;
+    }
+    double lc, lb, la, lL, lR;
+    bload(lc, S.lin, (uint32_t)r * lrowb + (uint32_t)pc * 8u, 0u);
+    bload(lb, S.lin, (uint32_t)rlo * lrowb + (uint32_t)pc * 8u, 0u);
+    bload(la, S.lin, (uint32_t)rhi * lrowb + (uint32_t)pc * 8u, 0u);
+    bload(lL, S.lin, (uint32_t)r * lrowb + (uint32_t)pl * 8u, 0u);
+    bload(lR, S.lin, (uint32_t)r * lrowb + (uint32_t)pr * 8u, 0u);
+
+    // moments: this lane's two rings (summed as raw_moments does), then the
+    // other lane's added
+    const real va = h == 0 ? (real)speed(1) : (real)speed(3), vb = h == 0 ? (real)speed(2) : (real)speed(4);
+    real rho = h == 0 ? x0 : (real)0, jx = 0, jy = 0, en = 0;
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+        const real *g = x + 4 * kk;  // directions 0..3 at g[0..3], 4..7 at g[8..11]
+        const real v = kk == 0 ? va : vb;
+        const real ring = ((g[0] + g[8]) + (g[2] + g[10])) + ((g[1] + g[9]) + (g[3] + g[11]));
+        const real a15 = g[1] - g[9], a37 = g[3] - g[11];
+        const real X = (g[0] - g[8]) + (real)SQH * (a15 - a37);
+        const real Y = (g[2] - g[10]) + (real)SQH * (a15 + a37);
+        rho += ring;
+        jx += v * X;
+        jy += v * Y;
+        en += (real)0.5 * v * v * ring;
+    }
+    Cell<real> C;
+    C.rho = rho + pair_swap(rho);
+    C.e = en + pair_swap(en);
+    C.init_moments(dp, jx + pair_swap(jx), jy + pair_swap(jy), lc);
+
+    const double ri = dp->r_min + ((double)r + 0.5) * dp->dr;
+    const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
+    real g[16];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+        const real v = kk == 0 ? va : vb;
+        const real Fk = h == 0 ? C.F[1 + kk] : C.F[3 + kk];
+        const real rF = C.rho * Fk;
+        const real Ak = C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T);
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) {
+            const int i = 4 * kk + dd;
+            const real z = v * C.EP.w(dd);
+            real pp, pm;
+            C.EP.eval(z, pp, pm);
+            const real bz = C.Bz * z;
+            const real acr = fabs(crv[dd]) * kr, act = fabs(ctv[dd]) * kt;
+            const real c0v = rF * pp * (Ak + bz) + C.omega * x[i];
+            const real c1v = rF * pm * (Ak - bz) + C.omega * x[i + 8];
+            g[i] = c0v - v * (acr * (x[i] - nbr[i]) + act * (x[i] - nbt[i]));
+            g[i + 8] = c1v - v * (acr * (x[i + 8] - nbr[i + 8]) + act * (x[i + 8] - nbt[i + 8]));
+        }
+    }
+    const double uxd = (double)C.ux, uyd = (double)C.uy;
+    const double urp = uxd * cs.x + uyd * cs.y;
+    const double utp = -uxd * cs.y + uyd * cs.x;
+    const double lr = urp >= 0.0 ? lb : la;
+    const double lt = utp >= 0.0 ? lL : lR;
+    const double lnew =
+        C.reacted(dp, lc) - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
+    if (e < count) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int dd = i & 3;
+            const bool first = (kctv[dd] >= (real)0) != (side == 1);  // keep direction dd, else dd + 4
+            ef[side][e][8 * h + i] = first ? g[i] : g[i + 8];
+        }
+        if (h == 0) el[side][e] = lnew;
+    }
+}
+
+// Orders this wavefront's LDS writes before its reads of what other lanes
+// wrote (a wavefront's LDS operations complete in order; this keeps the
+// compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Plane q of the ghost row beyond the grid made from row `src`: the copy of
+// the boundary row, with directions turned by 4 below the disc centre.
+__device__ __forceinline__ int ghost_plane(int q, bool turn)
+{
+    if (q == 0 || !turn) return q;
+    const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8;
+    return base + ((dir + 4) & 7);
+}
+
+// Fills the compact slots of the row behind (see stage_row) from a full row.
+template <typename real>
+__device__ __forceinline__ void fill_behind(real (*behind)[64], const real x[NQ], const bool mr[4], int lane)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int dd = 0; dd < 4; ++dd) behind[4 * k + dd][lane] = mr[dd] ? x[1 + 8 * k + dd] : x[5 + 8 * k + dd];
+}
+
+// Work of one wavefront of the two-step kernel: strip `strip`, rows [i0, i1)
+// (at most FUSE_ROWS), marched outward or, with `down`, inward.  Positions p
+// count rows in marching order from the first row of the block (p = 0);
+// stage A runs on positions -1 .. R where they are grid rows, stage B on
+// 0 .. R - 1, one position behind stage A.  LDS per wavefront: the compact
+// rows behind of f (fb) and of g (gb), the full row of g just computed (ga),
+// the edge cells (ef, el) and the gathered halo values of stage A's row
+// (hb, hbl).
+template <typename real>
+__device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
+                                       real (*fb)[64], real (*gb)[64], real (*ga)[64], real (*ef)[FUSE_ROWS][16],
+                                       double (*el)[FUSE_ROWS], real *hb, double *hbl, double redA[5],
+                                       double redB[5], bool diagA, bool diagB)
+{
+    const Strip<real, false> S(dp, bufs, strip);
+    edge_cells<real>(S, strip, i0, i1, ef, el);
+    wave_lds_sync();
+
+    const int lane = S.lane;
+    const double2 cs = dp->cs[S.pc];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    const real kr = (real)dp->dt_dr;
+    real acr[4];
+    bool mr[4], mt[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        acr[dd] = fabs(crv[dd]) * kr;
+        mr[dd] = (crv[dd] >= (real)0) != down;
+        mt[dd] = ctv[dd] >= (real)0;
+    }
+    const int nr = dp->nr;
+    const int step = down ? -1 : 1;
+    const int first = down ? i1 - 1 : i0;
+    const int count = i1 - i0;
+    const int rbefore = first - step, rafter = first + count * step;  // rows of positions -1 and R
+    const bool vlo = rbefore >= 0 && rbefore < nr, vhi = rafter >= 0 && rafter < nr;
+    const bool turn_lo = rbefore < 0 && dp->disc, turn_hi = rafter < 0 && dp->disc;
+
+    // f at positions p (fc) and p + 1 (fn) in registers; f(p + 2) is loaded
+    // into fc once stage A has used it, and the two swap at the end of the
+    // pass (the loop is not unrolled: one pass is already half the
+    // instruction cache)
+    real fc[NQ], fn[NQ];
+    double lp, lc, ln, lx = 0.0;             // lambda of f at positions p-1, p, p+1, p+2
+    double glp = 0.0, glc = 0.0, gln = 0.0;  // lambda of g at positions p-2, p-1, p
+    GatherHalo<real> hc, hn, hx;
+    int p0;
+    {
+        real t[NQ];
+        if (vlo) {
+            // stage A starts at position -1: behind it position -2 (a ghost
+            // beyond the grid), centre -1, ahead 0
+            S.load_row(rbefore, fc, lc);
+            S.load_halo(rbefore, hc.h, hc.hl);
+            S.load_row(first, fn, ln);
+            S.load_halo(first, hn.h, hn.hl);
+            row_or_ghost(S, rbefore - step, t, lp, fc, lc);
+            p0 = -1;
+        } else {
+            S.load_row(first, fc, lc);
+            S.load_halo(first, hc.h, hc.hl);
+            row_or_ghost(S, first + step, fn, ln, fc, lc);
+            if (count > 1 || vhi) S.load_halo(first + step, hn.h, hn.hl);
+            row_or_ghost(S, rbefore, t, lp, fc, lc);
+            p0 = 0;
+        }
+        fill_behind(fb, t, mr, lane);
+    }
+
+    for (int p = p0; p <= count; ++p) {
+        const int ir = first + p * step;
+        // g(p - 1), centre of stage B, before stage A replaces it in ga
+        real gc[NQ];
+        if (p >= 1) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) gc[q] = ga[q][lane];
+        } else if (p == 0 && vlo) {
+            // g(-1), computed by stage A at position -1, is the row behind
+            // stage B's first row
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd)
+                    gb[4 * k + dd][lane] = mr[dd] ? ga[1 + 8 * k + dd][lane] : ga[5 + 8 * k + dd][lane];
+        }
+        // (A) first step at position p, or the ghost beyond the grid
+        if (p < count || vhi) {
+            // the row's gathered halo values into LDS, read back by every lane
+            hb[lane] = hc.h[0];
+            if (lane < 2) {
+                hb[64 + lane] = hc.h[1];
+                hbl[lane] = hc.hl;
+            }
+            wave_lds_sync();
+            const LdsHalo<real> H{hb, hbl};
+            stage_row<real, true>(S, ir, fb, fc, fn, ga, H, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, gln,
+                                  redA, diagA && p >= 0 && p < count);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) ga[q][lane] = turn_hi ? gc[ghost_plane(q, true)] : gc[q];
+            gln = glc;
+        }
+        // f at position p + 2 (the row ahead of the next stage A) replaces f(p)
+        if (p + 1 < count || (p + 1 == count && vhi)) row_or_ghost(S, ir + 2 * step, fc, lx, fn, ln);
+        if (p + 2 < count || (p + 2 == count && vhi)) S.load_halo(ir + 2 * step, hx.h, hx.hl);
+        // (B) second step at position p - 1
+        if (p == 0 && !vlo) {
+            // the row behind stage B's first row is the ghost of g(0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int dd = 0; dd < 4; ++dd) {
+                    const real a = ga[ghost_plane(1 + 8 * k + dd, turn_lo)][lane];
+                    const real b = ga[ghost_plane(5 + 8 * k + dd, turn_lo)][lane];
+                    gb[4 * k + dd][lane] = mr[dd] ? a : b;
+                }
+            glc = gln;
+        } else if (p > 0) {
+            const int e = ir - step - i0;
+            const EdgeHalo<real> H{ef[0][e], ef[1][e], el[0][e], el[1][e]};
+            double unused;
+            stage_row<real, false>(S, ir - step, gb, gc, nullptr, ga, H, glp, glc, gln, mr, mt, acr, ctv, !down,
+                                   cs.x, cs.y, unused, redB, diagB);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const real t = fc[q];
+            fc[q] = fn[q];
+            fn[q] = t;
+        }
+        hc = hn;
+        hn = hx;
+        lp = lc;
+        lc = ln;
+        ln = lx;
+        glp = glc;
+        glc = gln;
+        // Compiler-only barrier: the LDS rows must not be promoted to
+        // registers across passes.
+        asm volatile("" ::: "memory");
+    }
+}
+
+// Steps `step` and step + 1 of one solve (descs[0]); tiles as k_step's.  One
+// wavefront per SIMD in both precisions (the two steps' rows fill the
+// register file and the LDS rows of four wavefronts most of a CU's LDS).
+template <typename real>
+__global__ __launch_bounds__(BLOCK, 1) void k_step2(const SolveDesc *descs, int ntiles,
+                                                                       int64_t step, int flip)
+{
+    const int nb = gridDim.x;
+    const int blk = xcd_tile(blockIdx.x, nb);
+    const int t = __builtin_amdgcn_readfirstlane(blk * (BLOCK / 64) + (threadIdx.x >> 6));
+    if (t >= ntiles) return;
+    const DescPtr dp = (DescPtr)descs;
+    const bool diagA = records(dp, step), diagB = records(dp, step + 1);
+    const int cur = (int)((step + flip) & 1);
+    const StepBufs bufs{dp->f[cur], dp->f[cur ^ 1], dp->lam[cur], dp->lam[cur ^ 1]};
+    __shared__ real fb[BLOCK / 64][16][64];
+    __shared__ real gb[BLOCK / 64][16][64];
+    __shared__ real ga[BLOCK / 64][NQ][64];
+    __shared__ real ef[BLOCK / 64][2][FUSE_ROWS][16];
+    __shared__ double el[BLOCK / 64][2][FUSE_ROWS];
+    __shared__ real hb[BLOCK / 64][66];
+    __shared__ double hbl[BLOCK / 64][2];
+    const int w = threadIdx.x >> 6;
+    double redA[5] = {0, 0, 0, 0, 0}, redB[5] = {0, 0, 0, 0, 0};
+    const int rows = dp->rows, nstrip = dp->nstrip;
+    const int rb = t / nstrip, strip = t - rb * nstrip;
+    const int i0 = rb * rows;
+    const int i1 = min(i0 + rows, dp->nr);
+    march2<real>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], redA,
+                 redB, diagA, diagB);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        if (!(s == 0 ? diagA : diagB)) continue;
+        const int64_t slot = ((step + s) / dp->diag_every) % PART_RING;
+        double *part = dp->wpart + ((size_t)slot * dp->nwaves + t) * 5;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double v = wave_sum(s == 0 ? redA[i] : redB[i]);
+            if ((threadIdx.x & 63) == 0) part[i] = v;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, hipStream_t st)
+{
+    const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_step2<double>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
+    return hipGetLastError();
+}
+
+}  // namespace pdbm

@@ -33,6 +33,22 @@ def test_host_and_device_kernel_names_match(src):
         assert host_kernels == dev_kernels, (host_kernels ^ dev_kernels)
 
 
+STEP_SOURCES = ("pdbm_step.hip", "pdbm_step2.hip")  # k_step and k_step2
+
+
+def _step_kernels_asm() -> str:
+    """gfx950 assembly of the sources holding the step kernels."""
+    out = []
+    with tempfile.TemporaryDirectory() as tmp:
+        for name in STEP_SOURCES:
+            dst = os.path.join(tmp, name + ".s")
+            cmd = [B.HIPCC, *[f for f in B.FLAGS if f not in ("-shared", "-fPIC")], f"-I{B.INCLUDE}", f"-I{B.CSRC}",
+                   "--cuda-device-only", "-S", os.path.join(B.CSRC, name), "-o", dst]
+            subprocess.run(cmd, cwd=tmp, check=True, capture_output=True)
+            out.append(open(dst).read())
+    return "\n".join(out)
+
+
 def _kernel_bodies(asm: str, key: str):
     for name in re.findall(r"^(_Z\S*" + key + r"\S*):", asm, flags=re.M):
         i = asm.index(name + ":")
@@ -47,13 +63,7 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
     selects afterwards.  Checked on the gfx950 assembly: no DPP shift of
     k_step sits between an exec-narrowing instruction and the matching
     restore."""
-    src = os.path.join(B.CSRC, "pdbm_kernels.hip")
-    with tempfile.TemporaryDirectory() as tmp:
-        out = os.path.join(tmp, "k.s")
-        cmd = [B.HIPCC, *[f for f in B.FLAGS if f not in ("-shared", "-fPIC")], f"-I{B.INCLUDE}", f"-I{B.CSRC}",
-               "--cuda-device-only", "-S", src, "-o", out]
-        subprocess.run(cmd, cwd=tmp, check=True, capture_output=True)
-        asm = open(out).read()
+    asm = _step_kernels_asm()
     bodies = list(_kernel_bodies(asm, "k_step"))
     assert len(bodies) == 5  # k_step: 2 precisions x (full annulus, rotated sector); k_step2: float64
     sreg = r"s\[\d+:\d+\]"
@@ -93,13 +103,7 @@ def test_step_kernel_uses_no_scratch_memory():
     spill to scratch memory inside the row loop adds memory round trips to
     every row.  Checked on the code-object metadata of every variant of the
     one-step and the two-step kernel."""
-    src = os.path.join(B.CSRC, "pdbm_kernels.hip")
-    with tempfile.TemporaryDirectory() as tmp:
-        out = os.path.join(tmp, "k.s")
-        cmd = [B.HIPCC, *[f for f in B.FLAGS if f not in ("-shared", "-fPIC")], f"-I{B.INCLUDE}", f"-I{B.CSRC}",
-               "--cuda-device-only", "-S", src, "-o", out]
-        subprocess.run(cmd, cwd=tmp, check=True, capture_output=True)
-        asm = open(out).read()
+    asm = _step_kernels_asm()
     seen = 0
     for block in asm.split("- .agpr_count:")[1:]:
         name = re.search(r"\.name:\s+(\S+)", block).group(1)
