@@ -69,7 +69,11 @@ enum { PDBM_QUEUED = 0, PDBM_RUNNING = 1, PDBM_DONE = 2, PDBM_FAILED = 3 }; /* r
 enum { PDBM_ALLOW_CFL = 1 };                                   /* flags       */
 
 /* Problem statement of one solve (Sec. II.D and III of the paper).
- *   nr, ntheta   cells in r and theta (>= 1, nr * ntheta <= 2^24)
+ *   nr, ntheta   cells in r and theta (>= 1, nr * ntheta <= 2^24, and one
+ *                f buffer, 33 * nr * pitch elements of 8 or 4 bytes with
+ *                pitch = ntheta rounded up to a multiple of 64, or 2 for
+ *                ntheta = 1, below 4 GiB: float64 grids up to about
+ *                4034 x 4000 cells, float32 up to 2^24 cells)
  *   sector       azimuthal extent s*pi/4, s in 1..8 (8 = full annulus).  The
  *                periodic theta halo rotates the direction index by s:
  *                f_{k,i}(j=-1) = f_{k,(i+s)%8}(ntheta-1),

@@ -142,3 +142,10 @@ def test_create_without_gpu_fails_loudly():
     with pytest.raises(P.PdbmError) as e:
         P.Solver(_good(), P.make_ic(**W.small_fp64().ic_kw()))
     assert e.value.code in (P.PDBM_ENOSYS, P.PDBM_EHIP)
+
+
+def test_empty_batch_is_refused():
+    # refused before any device call, so this runs without a GPU
+    with pytest.raises(P.PdbmError) as e:
+        P.Batch([], [])
+    assert e.value.code == P.PDBM_EINVAL

@@ -248,3 +248,33 @@ def test_server_submit_from_many_threads():
     st = srv.stats()
     assert st["submitted"] == 16 and st["done"] == 16
     srv.close()
+
+
+def test_zero_steps_change_nothing():
+    """Zero steps are a no-op for a solve and a pack, and a request for zero
+    steps comes back DONE with the initial fields; waiting on a server with
+    no requests returns at once."""
+    w = _small_sweep(1, seed=10)[0]
+    for prec in (P.PDBM_FP64, P.PDBM_FP32):
+        s = P.Solver(_params(w, prec), P.make_ic(**w.ic_kw()))
+        F0, _ = s.moments()
+        f0, l0 = s.read_f()
+        s.step(0)
+        assert s.step_count == 0
+        f1, l1 = s.read_f()
+        assert np.array_equal(f0, f1) and np.array_equal(l0, l1)
+        b = P.Batch([_params(w, prec)], [P.make_ic(**w.ic_kw())], chunk_steps=5)
+        b.step(0)
+        assert b.step_count(0) == 0
+        assert np.array_equal(b.moments(0)[0], F0)
+        srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=2, chunk_steps=5)
+        t0 = time.perf_counter()
+        assert srv.wait(10.0)
+        assert time.perf_counter() - t0 < 1.0
+        rid = srv.submit(_params(w, prec), P.make_ic(**w.ic_kw()), 0, keep_fields=True)
+        assert srv.wait(60.0)
+        state, F, _ = srv.poll(rid, fields=True)
+        assert state == P.PDBM_DONE
+        assert np.array_equal(F, F0)
+        assert srv.stats()["done"] == 1
+        srv.close()
