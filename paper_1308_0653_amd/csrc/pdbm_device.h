@@ -1,6 +1,8 @@
 // Device code shared by the kernels of libpdbm for gfx950 (MI355X): the
 // per-cell arithmetic of the method, wavefront reductions, lane shifts, raw
-// buffer access and the wavefront strip over the paired f layout.
+// buffer access and the wavefront strip over the paired f layout.  It sits
+// in an unnamed namespace on purpose: each kernel source compiles its own
+// internal copy, and no device symbol is shared between the sources.
 //
 // One cell per lane.  Within an r row, f holds the rest particle's plane and
 // the 16 pairs of opposite directions interleaved per column (elem_of), so
