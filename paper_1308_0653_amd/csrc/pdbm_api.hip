@@ -25,11 +25,10 @@ constexpr int64_t MAX_CELLS = int64_t(1) << 24;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Padded row length: a multiple of the 64 columns of one wavefront, so that
-// every wavefront's store of one velocity plane covers whole cache lines.
-// Rows are padded to whole 64-column strips (a strip's loads and stores
-// then cover whole cache lines); a single column gets a pitch of 2, so that
-// the pairs of the f layout stay 16-byte aligned.
+// Padded row length: whole 64-column strips, so that a wavefront's loads and
+// stores of a velocity plane or pair cover whole cache lines; a single
+// column gets a pitch of 2, which keeps the pairs of the f layout 16-byte
+// aligned.
 int pitch_of(int nt) { return nt == 1 ? 2 : (nt + STRIP - 1) / STRIP * STRIP; }
 
 bool is_fin(double x) { return std::isfinite(x); }
