@@ -52,6 +52,14 @@
  *   R16 P^m with integer m by repeated multiplication.
  *   R17 lambda is not clamped.
  *   R18 If the reaction is gated off or a+b = 0: lambda_reac = lambda.
+ *
+ * Parity unpinned: readings R7, R8 and R12.  The tests pin every other part
+ * of this file to values the paper or the mathematics fix.  Nothing the
+ * paper prints separates these three choices from their alternatives: the
+ * explicit rate R inside M against an effective rate taken from the
+ * closed-form lambda step (R7), the unsplit update against a split one
+ * (R8), and the zero-gradient radial ghosts beyond the invariance of a
+ * uniform state (R12).
  */
 #include <stdint.h>
 #include <stdlib.h>
