@@ -66,20 +66,24 @@ def test_batch_members_match_single_solves_and_oracle(chunk):
             assert _rel(F[k], R[k]) < 1e-10, (i, k)
 
 
-def test_batch_graph_replay_equals_plain_launches():
+@pytest.mark.parametrize("precision", [P.PDBM_FP32, P.PDBM_FP64])
+def test_batch_graph_replay_equals_plain_launches(precision):
+    """Chunks replayed from the captured graph against plain launches, after
+    every call: whole chunks, remainders run as plain launches in between,
+    and the synchronising moments reads between the replays."""
     ws = _small_sweep(3, seed=2)
-    params = [_params(w, P.PDBM_FP32, diag_every=4) for w in ws]
+    params = [_params(w, precision, diag_every=4) for w in ws]
     ics = [P.make_ic(**w.ic_kw()) for w in ws]
     a = P.Batch(params, ics, chunk_steps=6)
     b = P.Batch(params, ics, chunk_steps=0)
-    for n in (13, 6, 1, 12):  # whole chunks and remainders
+    for n in (13, 6, 1, 12, 6, 18):  # whole chunks and remainders
         a.step(n)
         b.step(n)
-    for i in range(len(ws)):
-        Fa, da = a.moments(i)
-        Fb, db = b.moments(i)
-        assert np.array_equal(Fa, Fb)
-        assert da == db
+        for i in range(len(ws)):
+            Fa, da = a.moments(i)
+            Fb, db = b.moments(i)
+            assert np.array_equal(Fa, Fb), (n, i)
+            assert da == db, (n, i)
 
 
 def test_batch_member_alone_equals_in_mix_fp32():
