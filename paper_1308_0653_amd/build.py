@@ -17,6 +17,11 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep loop-invariant constants (for example those of exp() in the
+    # reaction step) out of registers held across the step kernels' row
+    # loops: hoisted, they are spilled to scratch by the float32 two-step
+    # kernel, which has 256 registers per lane
+    "-mllvm", "-disable-machine-licm",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 

@@ -346,7 +346,7 @@ bool Solve::fusable() const
         const char *e = std::getenv("PDBM_FUSE");
         return e && e[0] == '0';
     }();
-    return !off && !fp32 && !rot() && p.ntheta > 1 && L.rows <= FUSE_ROWS;
+    return !off && !rot() && p.ntheta > 1 && L.rows <= FUSE_ROWS;
 }
 
 int Solve::reduce_records(hipStream_t st)
@@ -440,7 +440,7 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
     const bool pairs = s.fusable();
     for (int64_t i = 0; i < nsteps;) {
         if (pairs && nsteps - i >= 2) {
-            HIPCHK(launch_step2(s.dd, s.waves(), s.step, s.flip, h->st));
+            HIPCHK(launch_step2(s.dd, s.waves(), s.step, s.flip, s.fp32, h->st));
             s.step += 2;
             s.flip ^= 1;
             i += 2;

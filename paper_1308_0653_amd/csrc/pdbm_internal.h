@@ -84,12 +84,12 @@ struct DiagCtl {
 // flip = 0, a single solve the parity its two-step launches have left.
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
                        int flip, bool fp32, bool rot, hipStream_t st);
-// Steps `step` and step + 1 of the single float64 solve descs[0] in one
+// Steps `step` and step + 1 of the single solve descs[0] in one
 // pass: reads buffer (step + flip) & 1 and writes the other one, so the
 // caller toggles flip.  Full annulus only (no rotated sector images), ntheta
 // > 1, rows per wavefront at most FUSE_ROWS, step + 2 <= nsteps.  Makes the
 // drift records of both steps as launch_step does.
-hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, hipStream_t st);
+hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, bool fp32, hipStream_t st);
 // Non-equilibrium measures (Sec. II.E) of the state in buffer `cur` into
 // device memory out [NONEQ][nr][nt] float64.
 hipError_t launch_noneq(const SolveDesc &d, int cur, bool fp32, double *out, hipStream_t st);

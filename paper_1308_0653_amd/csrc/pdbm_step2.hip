@@ -51,20 +51,92 @@ struct EdgeHalo {
     __device__ __forceinline__ double lright() const { return lr; }
 };
 
+// Sum of x over the wavefront (every lane active), in a fixed order: pairs,
+// quads, half rows and rows of 16 lanes by DPP (after which every lane of a
+// row holds the row's sum), then rows 1 and 3 add rows 0 and 2 by broadcast
+// of lanes 15 and 47, and rows 2 and 3 the first half by broadcast of lane
+// 31.  Lane 63 ends with the total, which is returned to every lane.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double x)
+{
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, false);
+    return x + __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_total(double x)
+{
+    x = dpp_add<0xB1, 0xf>(x);   // quad_perm [1, 0, 3, 2]
+    x = dpp_add<0x4E, 0xf>(x);   // quad_perm [2, 3, 0, 1]
+    x = dpp_add<0x141, 0xf>(x);  // row_half_mirror
+    x = dpp_add<0x140, 0xf>(x);  // row_mirror
+    x = dpp_add<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x = dpp_add<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 63),
+                            __builtin_amdgcn_readlane(__double2loint(x), 63));
+}
+
+// Drift sums of one step (mass, energy, chemical energy, non-finite and
+// non-physical cells; see diag_cell).  LaneDiag keeps per-lane partial sums
+// over the whole march, added across the wavefront at the end.  RowDiag adds
+// each row across the wavefront at once and keeps the wavefront's running
+// sums in LDS (acc) and its counts in scalar registers, so that no per-lane
+// accumulator stays live through the march: the float32 kernel runs two
+// wavefronts per SIMD and has no registers to spare for them.
+struct LaneDiag {
+    double red[5] = {0, 0, 0, 0, 0};
+    __device__ __forceinline__ explicit LaneDiag(double *) {}
+    __device__ __forceinline__ void add(bool valid, double rho, double ux, double uy, double T, double e, double lam,
+                                        double w, double Q)
+    {
+        if (valid) diag_cell(red, rho, ux, uy, T, e, lam, w, Q);
+    }
+    __device__ __forceinline__ double total(int i) const { return wave_sum(red[i]); }
+};
+struct RowDiag {
+    double *acc;  // LDS, 3 doubles of this wavefront
+    int nonfinite = 0, nonphys = 0;
+    __device__ __forceinline__ explicit RowDiag(double *a) : acc(a)
+    {
+        acc[0] = acc[1] = acc[2] = 0.0;
+    }
+    // every lane calls this; `valid`: the lane holds a cell of the grid
+    __device__ __forceinline__ void add(bool valid, double rho, double ux, double uy, double T, double e, double lam,
+                                        double w, double Q)
+    {
+        const bool finite = isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy) && isfinite(lam);
+        const bool use = valid && finite;
+        nonfinite += __popcll(__ballot(valid && !finite));
+        nonphys += __popcll(__ballot(use && (rho <= 0.0 || T <= 0.0)));
+        const double m = wave_total(use ? rho * w : 0.0);
+        const double en = wave_total(use ? e * w : 0.0);
+        const double ch = wave_total(use ? rho * Q * (1.0 - lam) * w : 0.0);
+        acc[0] += m;
+        acc[1] += en;
+        acc[2] += ch;
+    }
+    __device__ __forceinline__ double total(int i) const
+    {
+        return i < 3 ? acc[i] : (double)(i == 3 ? nonfinite : nonphys);
+    }
+};
+
 // One row of one of the two steps: the arithmetic of update_row, with the
 // azimuthal halo from H.  Radial neighbours: the row behind in compact LDS
 // slots (of each opposite pair of directions only the one that takes its
 // upwind value from behind, slot 4 (k - 1) + (direction mod 4); replaced by
 // this row's as they are read), the row ahead in `fn` (stage A) or in the
 // full LDS row `ga` (stage B).  STAGEA: the new row goes to `ga` and `lout`,
-// for every lane (stage B reads the periodic images too); otherwise it is
-// stored, for the strip's own columns.
-template <typename real, bool STAGEA, class Halo>
+// for every lane (stage B reads the periodic images too), and the row it
+// replaces in `ga` to `gold`, plane by plane, so that the registers of the
+// old row fill as those of fc empty; otherwise it is stored, for the strip's
+// own columns.
+template <typename real, bool STAGEA, class Halo, class Diag>
 __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, real (*behind)[64], const real fc[NQ],
-                                          const real *fn, real (*ga)[64], const Halo &H, double lbehind, double lc,
+                                          const real *fn, real (*ga)[64], real *gold, const Halo &H, double lbehind,
+                                          double lc,
                                           double lahead, const bool mr[4], const bool mt[4], const real acr[4],
                                           const real ctv[4], bool lr_behind, double csx, double csy, double &lout,
-                                          double red[5], bool diag)
+                                          Diag &D, bool diag)
 {
     const DescPtr dp = S.dp;
     const Cell<real> C(dp, fc, lc);
@@ -85,10 +157,12 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
     // lane mask, which keeps the exec-mask branches and their registers out
     // of the row loop
     const real rest = C.rest(fc[0]);
-    if (STAGEA)
+    if (STAGEA) {
+        gold[0] = ga[0][lane];
         ga[0][lane] = rest;
-    else
+    } else {
         bstore(rest, S.fout, S.vos, rowoff);
+    }
 #pragma unroll
     for (int k = 1; k <= 4; ++k) {
         const real v = (real)speed(k);
@@ -129,7 +203,10 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
         }
         if (STAGEA) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) ga[base + i][lane] = o[i];
+            for (int i = 0; i < 8; ++i) {
+                gold[base + i] = ga[base + i][lane];
+                ga[base + i][lane] = o[i];
+            }
         } else {
 #pragma unroll
             for (int dd = 0; dd < 4; ++dd)
@@ -151,7 +228,7 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
     else
         bstore(lnew, S.lout, S.vols, (uint32_t)ir * S.lrow_bytes);
 
-    if (diag && store) diag_cell(red, (double)C.rho, uxd, uyd, C.Td, (double)C.e, lc, ri * dp->dr * dp->dth, dp->Q);
+    if (diag) D.add(store, (double)C.rho, uxd, uyd, C.Td, (double)C.e, lc, ri * dp->dr * dp->dth, dp->Q);
 }
 
 // The value the other lane of a lane pair (lanes 2m, 2m + 1) holds.
@@ -335,11 +412,11 @@ __device__ __forceinline__ void fill_behind(real (*behind)[64], const real x[NQ]
 // rows behind of f (fb) and of g (gb), the full row of g just computed (ga),
 // the edge cells (ef, el) and the gathered halo values of stage A's row
 // (hb, hbl).
-template <typename real>
+template <typename real, class Diag>
 __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
                                        real (*fb)[64], real (*gb)[64], real (*ga)[64], real (*ef)[FUSE_ROWS][16],
-                                       double (*el)[FUSE_ROWS], real *hb, double *hbl, double redA[5],
-                                       double redB[5], bool diagA, bool diagB)
+                                       double (*el)[FUSE_ROWS], real *hb, double *hbl, Diag &DA, Diag &DB,
+                                       bool diagA, bool diagB)
 {
     const Strip<real, false> S(dp, bufs, strip);
     edge_cells<real>(S, strip, i0, i1, ef, el);
@@ -400,12 +477,10 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
 
     for (int p = p0; p <= count; ++p) {
         const int ir = first + p * step;
-        // g(p - 1), centre of stage B, before stage A replaces it in ga
+        // g(p - 1), centre of stage B: stage A hands it over as it replaces
+        // it in ga
         real gc[NQ];
-        if (p >= 1) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) gc[q] = ga[q][lane];
-        } else if (p == 0 && vlo) {
+        if (p == 0 && vlo) {
             // g(-1), computed by stage A at position -1, is the row behind
             // stage B's first row
 #pragma unroll
@@ -424,9 +499,11 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
             }
             wave_lds_sync();
             const LdsHalo<real> H{hb, hbl};
-            stage_row<real, true>(S, ir, fb, fc, fn, ga, H, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, gln,
-                                  redA, diagA && p >= 0 && p < count);
+            stage_row<real, true>(S, ir, fb, fc, fn, ga, gc, H, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, gln,
+                                  DA, diagA && p >= 0 && p < count);
         } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) gc[q] = ga[q][lane];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) ga[q][lane] = turn_hi ? gc[ghost_plane(q, true)] : gc[q];
             gln = glc;
@@ -450,8 +527,8 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
             const int e = ir - step - i0;
             const EdgeHalo<real> H{ef[0][e], ef[1][e], el[0][e], el[1][e]};
             double unused;
-            stage_row<real, false>(S, ir - step, gb, gc, nullptr, ga, H, glp, glc, gln, mr, mt, acr, ctv, !down,
-                                   cs.x, cs.y, unused, redB, diagB);
+            stage_row<real, false>(S, ir - step, gb, gc, nullptr, ga, nullptr, H, glp, glc, gln, mr, mt, acr, ctv, !down,
+                                   cs.x, cs.y, unused, DB, diagB);
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -472,11 +549,26 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
     }
 }
 
-// Steps `step` and step + 1 of one solve (descs[0]); tiles as k_step's.  One
-// wavefront per SIMD in both precisions (the two steps' rows fill the
-// register file and the LDS rows of four wavefronts most of a CU's LDS).
+// Drift accumulators of the two-step kernel: per lane in float64 (one
+// wavefront per SIMD, with room in the AGPRs), per row in float32 (two
+// wavefronts per SIMD).
 template <typename real>
-__global__ __launch_bounds__(BLOCK, 1) void k_step2(const SolveDesc *descs, int ntiles,
+struct DiagOf {
+    using type = LaneDiag;
+    static constexpr int waves = 1;
+};
+template <>
+struct DiagOf<float> {
+    using type = RowDiag;
+    static constexpr int waves = 2;
+};
+
+// Steps `step` and step + 1 of one solve (descs[0]); tiles as k_step's.  One
+// wavefront per SIMD in float64, where the two steps' rows fill the register
+// file and the LDS rows of four wavefronts most of a CU's LDS; two in
+// float32, whose rows take half the LDS.
+template <typename real>
+__global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const SolveDesc *descs, int ntiles,
                                                                        int64_t step, int flip)
 {
     const int nb = gridDim.x;
@@ -494,14 +586,16 @@ __global__ __launch_bounds__(BLOCK, 1) void k_step2(const SolveDesc *descs, int 
     __shared__ double el[BLOCK / 64][2][FUSE_ROWS];
     __shared__ real hb[BLOCK / 64][66];
     __shared__ double hbl[BLOCK / 64][2];
+    __shared__ double dacc[BLOCK / 64][2][3];
     const int w = threadIdx.x >> 6;
-    double redA[5] = {0, 0, 0, 0, 0}, redB[5] = {0, 0, 0, 0, 0};
+    using Diag = typename DiagOf<real>::type;
+    Diag DA(dacc[w][0]), DB(dacc[w][1]);
     const int rows = dp->rows, nstrip = dp->nstrip;
     const int rb = t / nstrip, strip = t - rb * nstrip;
     const int i0 = rb * rows;
     const int i1 = min(i0 + rows, dp->nr);
-    march2<real>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], redA,
-                 redB, diagA, diagB);
+    march2<real>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], DA, DB,
+                 diagA, diagB);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         if (!(s == 0 ? diagA : diagB)) continue;
@@ -509,7 +603,7 @@ __global__ __launch_bounds__(BLOCK, 1) void k_step2(const SolveDesc *descs, int 
         double *part = dp->wpart + ((size_t)slot * dp->nwaves + t) * 5;
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
-            const double v = wave_sum(s == 0 ? redA[i] : redB[i]);
+            const double v = s == 0 ? DA.total(i) : DB.total(i);
             if ((threadIdx.x & 63) == 0) part[i] = v;
         }
     }
@@ -517,11 +611,14 @@ __global__ __launch_bounds__(BLOCK, 1) void k_step2(const SolveDesc *descs, int 
 
 }  // namespace
 
-hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, hipStream_t st)
+hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, bool fp32, hipStream_t st)
 {
     const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_step2<double>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
+    if (fp32)
+        hipLaunchKernelGGL(k_step2<float>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
+    else
+        hipLaunchKernelGGL(k_step2<double>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
     return hipGetLastError();
 }
 

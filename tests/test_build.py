@@ -60,12 +60,14 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
     shifts.  A shift executed while some lanes are switched off (inside a
     divergent branch) reads 0 from those lanes, silently corrupting their
     neighbours' update; the source takes every shift unconditionally and
-    selects afterwards.  Checked on the gfx950 assembly: no DPP shift of
-    k_step sits between an exec-narrowing instruction and the matching
-    restore."""
+    selects afterwards.  The same holds for the other cross-lane DPP moves
+    (the lane-pair swap of the two-step kernel's edge cells, the wavefront
+    totals of its float32 drift sums).  Checked on the gfx950 assembly: no
+    DPP instruction of k_step or k_step2 sits between an exec-narrowing
+    instruction and the matching restore."""
     asm = _step_kernels_asm()
     bodies = list(_kernel_bodies(asm, "k_step"))
-    assert len(bodies) == 5  # k_step: 2 precisions x (full annulus, rotated sector); k_step2: float64
+    assert len(bodies) == 6  # k_step: 2 precisions x (full annulus, rotated sector); k_step2: 2 precisions
     sreg = r"s\[\d+:\d+\]"
     for name, lines in bodies:
         # An exec-narrowing region opens with s_and_saveexec_b64 sX (on every
@@ -74,7 +76,7 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
         # The mask may move on the way (s_xor_b64 sA, exec, sX before an
         # else-arm, s_or_saveexec_b64 / s_andn2_saveexec_b64 sA, sX, s_mov):
         # each region is the set of registers its mask has been copied to.
-        regions, shifts, narrowed = [], 0, 0
+        regions, shifts, dpp, narrowed = [], 0, 0, 0
         for line in lines:
             t = line.strip()
             m = re.match(r"s_and_saveexec_b64\s+(" + sreg + ")", t)
@@ -93,8 +95,11 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
                 regions = [reg for reg in regions if m.group(1) not in reg]
             if "wave_shr:1" in t or "wave_shl:1" in t:
                 shifts += 1
+            if re.search(r"\b(wave_sh[lr]|row_|quad_perm)", t):
+                dpp += 1
                 narrowed += bool(regions)
         assert shifts >= 66, (name, shifts)
+        assert dpp >= shifts, (name, dpp)
         assert narrowed == 0, (name, narrowed)
 
 
@@ -111,4 +116,4 @@ def test_step_kernel_uses_no_scratch_memory():
             continue
         seen += 1
         assert int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1)) == 0, name
-    assert seen == 5
+    assert seen == 6

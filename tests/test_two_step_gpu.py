@@ -1,10 +1,10 @@
 """Two steps per launch against one step per launch.
 
-Solver.step(n) advances a full-annulus float64 solve with ntheta > 1 in
-pairs of steps, each pair in one pass over f (k_step2); step(1) always takes
-the one-step kernel, and float32 solves always step one at a time (their
-cases here check the step loop itself).  Both do the same arithmetic per cell in the same order, so
-their states agree to rounding.  The cases cover strip and row-block edges
+Solver.step(n) advances a full-annulus solve with ntheta > 1 in pairs of
+steps, each pair in one pass over f (k_step2: one wavefront per SIMD in
+float64, two in float32, whose drift sums are added across the wavefront row
+by row); step(1) always takes the one-step kernel.  Both do the same
+arithmetic per cell in the same order, so their states agree to rounding.  The cases cover strip and row-block edges
 (blocks of one row up to the 16-row limit, marched both ways), the disc
 centre, both precisions, odd step counts (pairs and one single step), the
 drift records of both steps of a pair, and checkpoints taken after an odd
@@ -40,9 +40,12 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-# float64 agrees to a few units in the last place; float32 state values are
-# compared relative to their own scale
-TOL = {P.PDBM_FP64: 1e-13, P.PDBM_FP32: 1e-6}
+# The two paths round differently (the compiler contracts multiply-adds per
+# inlined context, and the float32 form converts to and from float64 in
+# places): after 7 steps float64 differs by up to about 15 units of its
+# rounding (1.7e-15) and float32 by up to about 30 of its own (1.9e-6, disc
+# case), relative to the largest f.  The bounds allow about 100 and 160.
+TOL = {P.PDBM_FP64: 1e-13, P.PDBM_FP32: 1e-5}
 
 
 @pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
@@ -68,11 +71,17 @@ def test_pairs_match_single_steps(precision, nr, nt, r_min):
     assert np.abs(Fa - Fb).max() <= TOL[precision] * max(np.abs(Fb).max(), 1.0)
 
 
-def test_pair_drift_records_match_single_steps():
+# drift sums of states equal to rounding: float32 states differ in the last
+# bits of f between the two paths
+DTOL = {P.PDBM_FP64: 1e-13, P.PDBM_FP32: 1e-6}
+
+
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_pair_drift_records_match_single_steps(precision):
     w = _case(33, 130)
-    a = _solver(w, P.PDBM_FP64, diag_every=1)
+    a = _solver(w, precision, diag_every=1)
     a.step(130)  # more records than the partial-sum ring holds
-    b = _solver(w, P.PDBM_FP64, diag_every=1)
+    b = _solver(w, precision, diag_every=1)
     for _ in range(130):
         b.step(1)
     ha, hb = a.diag_history(), b.diag_history()
@@ -81,7 +90,7 @@ def test_pair_drift_records_match_single_steps():
         assert ra["step"] == rb["step"]
         assert ra["n_nonfinite"] == rb["n_nonfinite"] == 0 and ra["n_nonphys"] == rb["n_nonphys"] == 0
         for k in ("mass", "energy", "chem"):
-            assert abs(ra[k] - rb[k]) <= 1e-13 * abs(rb[k]), (ra, rb)
+            assert abs(ra[k] - rb[k]) <= DTOL[precision] * abs(rb[k]), (ra, rb)
 
 
 @pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
@@ -105,20 +114,21 @@ def test_checkpoint_after_odd_number_of_pairs(precision):
     assert np.array_equal(a.noneq(), ref.noneq())
 
 
-def test_pair_drift_records_every_third_step():
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_pair_drift_records_every_third_step(precision):
     """Records every third step: a pair holds one record step or none, and
     the records of both kinds of pair match single steps."""
     w = _case(20, 70)
-    a = _solver(w, P.PDBM_FP64, diag_every=3)
+    a = _solver(w, precision, diag_every=3)
     a.step(61)
-    b = _solver(w, P.PDBM_FP64, diag_every=3)
+    b = _solver(w, precision, diag_every=3)
     for _ in range(61):
         b.step(1)
     ha, hb = a.diag_history(), b.diag_history()
     assert [r["step"] for r in ha] == [r["step"] for r in hb] == list(range(0, 61, 3))
     for ra, rb in zip(ha, hb):
         for k in ("mass", "energy", "chem"):
-            assert abs(ra[k] - rb[k]) <= 1e-13 * abs(rb[k]), (ra, rb)
+            assert abs(ra[k] - rb[k]) <= DTOL[precision] * abs(rb[k]), (ra, rb)
 
 
 @pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
@@ -145,4 +155,32 @@ def test_pairs_from_an_odd_step_after_restore(precision):
     ha, hb = a.diag_history(), b.diag_history()
     assert [r["step"] for r in ha] == [r["step"] for r in hb] == list(range(7, 16))
     for ra, rb in zip(ha, hb):
-        assert abs(ra["mass"] - rb["mass"]) <= 1e-12 * abs(rb["mass"])
+        assert abs(ra["mass"] - rb["mass"]) <= max(DTOL[precision], 1e-12) * abs(rb["mass"])
+
+
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_pair_drift_counts_match_single_steps(precision):
+    """Non-finite and non-physical cells in the drift records: one cell of
+    NaN f (whose NaN reaches its four neighbours in each step) and one cell
+    with every f negated (rho < 0, T unchanged), both inside strips and
+    rows, far apart.  The counts of pairs equal those of single steps, and
+    the sums, which leave non-finite cells out, agree."""
+    w = _case(40, 130)
+    a = _solver(w, precision, diag_every=1)
+    f, lam = a.read_f()
+    f[:, 10, 30] = np.nan
+    f[:, 30, 100] *= -1.0
+    a.write_f(f, lam)
+    b = _solver(w, precision, diag_every=1)
+    b.write_f(f, lam)
+    a.step(2)
+    b.step(1)
+    b.step(1)
+    ha, hb = a.diag_history(), b.diag_history()
+    assert [r["step"] for r in ha] == [r["step"] for r in hb] == [0, 1]
+    assert ha[0]["n_nonfinite"] == hb[0]["n_nonfinite"] == 1
+    assert ha[1]["n_nonfinite"] == hb[1]["n_nonfinite"] == 5
+    assert ha[0]["n_nonphys"] == hb[0]["n_nonphys"] == 1
+    for ra, rb in zip(ha, hb):
+        for k in ("mass", "energy", "chem"):
+            assert np.isfinite(ra[k]) and abs(ra[k] - rb[k]) <= DTOL[precision] * abs(rb[k]), (ra, rb)
