@@ -17,7 +17,7 @@
  *      (Sec. II.C-D); the reaction progress lambda is integrated in closed
  *      form and advected upwind by the cell's own u (Sec. III.A).
  * All four run in one fused kernel launch per step on the caller's stream
- * (float64 full-annulus solves: one launch per two steps, see pdbm_step).
+ * (full-annulus solves: one launch per two steps, see pdbm_step).
  *
  * Conventions
  *   - Every entry point returns 0 (PDBM_OK) or a negative PDBM_E* code;
@@ -178,11 +178,11 @@ int pdbm_set_fields(pdbm_solver *s, const double *fields);
 
 /* Enqueues `nsteps` time steps on the solver's stream and returns without
  * waiting.  Every diag_every-th step also records the drift report of the
- * state it starts from.  Float64 solves of the full annulus with ntheta > 1
- * take the steps two per launch (one pass over f for both; the result equals
- * that of single steps to rounding), and an odd count ends with a single
- * step; the states after every call are those of Sec. II.C's scheme either
- * way. */
+ * state it starts from.  Solves of the full annulus with ntheta > 1, in
+ * either precision, take the steps two per launch (one pass over f for both;
+ * the result equals that of single steps to rounding), and an odd count ends
+ * with a single step; the states after every call are those of Sec. II.C's
+ * scheme either way. */
 int pdbm_step(pdbm_solver *s, int64_t nsteps);
 
 /* Number of steps taken so far (host-side counter). */
