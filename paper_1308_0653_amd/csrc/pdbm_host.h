@@ -64,9 +64,9 @@ class Solve {
     void release();  // frees an owned workspace (the stream must be idle)
 
     int cur() const { return (int)((step + flip) & 1); }
-    // Whether two steps may go in one launch: float64 (in float32 the one-step
-    // kernel, at two wavefronts per SIMD, is faster), full annulus, ntheta >
-    // 1, row blocks of at most FUSE_ROWS rows.
+    // Whether two steps may go in one launch: full annulus, ntheta > 1, row
+    // blocks of at most FUSE_ROWS rows (either precision; PDBM_FUSE=0 turns
+    // it off).
     bool fusable() const;
     int waves() const { return L.nwaves; }
     bool rot() const { return p.sector != 8; }

@@ -1,5 +1,6 @@
-// Two time steps per launch, in one pass over f (k_step2): float64 solves
-// of the full annulus with more than one theta column.
+// Two time steps per launch, in one pass over f (k_step2): single solves of
+// the full annulus with more than one theta column, in float64 (one
+// wavefront per SIMD) and float32 (two).
 #include "pdbm_device.h"
 
 namespace pdbm {
