@@ -39,7 +39,8 @@
  *   PDBM_ROWS_PER_WAVE=n   r rows per wavefront of single solves (created
  *                          after it is set); above 16 disables two-step
  *                          launches.
- *   PDBM_BATCH_ROWS=n      r rows per wavefront of packed launches (4).
+ *   PDBM_BATCH_ROWS=n      r rows per wavefront of packed launches (16 for
+ *                          solves that step in pairs, 4 for the others).
  */
 #ifndef PDBM_H
 #define PDBM_H
@@ -240,12 +241,13 @@ int pdbm_get_state(pdbm_solver *s, void *buf, size_t *bytes);
 int pdbm_set_state(pdbm_solver *s, const void *buf, size_t bytes);
 
 /* -------------------------------------------------------- packed batch -- */
-enum { PDBM_MAX_CHUNK = 64 }; /* longest run of launches captured in one graph */
+enum { PDBM_MAX_CHUNK = 64 }; /* most steps captured in one graph */
 
 /* A fixed set of independent solves (each with its own grid, parameters and
- * initial state; all of one precision) advanced together: one launch of the
- * step kernel steps every member, and runs of `chunk_steps` launches are
- * captured once in a HIP graph and replayed (chunk_steps = 0: plain
+ * initial state; all of one precision) advanced together: one launch takes
+ * every member two steps (one step where a count is odd, and one per launch
+ * in packs holding a rotated sector or a single theta column), and runs of
+ * `chunk_steps` steps are captured once in a HIP graph and replayed (chunk_steps = 0: plain
  * launches; at most PDBM_MAX_CHUNK, else PDBM_EINVAL).  Graphs need a stream other than the null stream: with
  * stream = NULL and chunk_steps > 1 the batch creates a stream of its own.
  * Each member's fields are bitwise those it would have alone in a batch of

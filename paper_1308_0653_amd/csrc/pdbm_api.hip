@@ -440,12 +440,12 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
     const bool pairs = s.fusable();
     for (int64_t i = 0; i < nsteps;) {
         if (pairs && nsteps - i >= 2) {
-            HIPCHK(launch_step2(s.dd, s.waves(), s.step, s.flip, s.fp32, h->st));
+            HIPCHK(launch_step2(s.dd, nullptr, s.waves(), nullptr, s.step, nullptr, s.flip, false, s.fp32, h->st));
             s.step += 2;
             s.flip ^= 1;
             i += 2;
         } else {
-            HIPCHK(launch_step(s.dd, nullptr, s.waves(), nullptr, s.step, s.flip, s.fp32, s.rot(), h->st));
+            HIPCHK(launch_step(s.dd, nullptr, s.waves(), nullptr, s.step, nullptr, s.flip, s.fp32, s.rot(), h->st));
             s.step += 1;
             i += 1;
         }

@@ -21,7 +21,10 @@ int fail(int code, const std::string &msg);
         if (e_ != hipSuccess) return ::pdbm::fail(PDBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int DEFAULT_BATCH_ROWS = 4;  // rows per wavefront in packed launches (many rounds of short wavefronts balance best)
+// Rows per wavefront in packed launches: packs of one step per launch
+// balance best with many rounds of short wavefronts; two-step launches
+// recompute fewer rows with the longest blocks the two-step kernel takes.
+constexpr int ONE_STEP_BATCH_ROWS = 4;
 
 // Device memory of one solve, in this order (all offsets 256-byte aligned).
 struct Layout {

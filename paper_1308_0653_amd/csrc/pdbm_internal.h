@@ -80,21 +80,28 @@ struct DiagCtl {
 // The step a solve takes is bases[solve] + step_off (bases NULL: step_off);
 // a solve whose step is at or beyond its nsteps is left alone.  A step that
 // makes a drift record leaves partial sums that launch_records adds up.
-// The state of step s lives in buffer (s + flip) & 1: packed launches pass
-// flip = 0, a single solve the parity its two-step launches have left.
+// The state of step s of solve i lives in buffer (s + flip_i) & 1, flip_i =
+// flips[i] ^ flip (flips NULL: flip), the parity its two-step launches have
+// left.
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
-                       int flip, bool fp32, bool rot, hipStream_t st);
-// Steps `step` and step + 1 of the single solve descs[0] in one
-// pass: reads buffer (step + flip) & 1 and writes the other one, so the
-// caller toggles flip.  Full annulus only (no rotated sector images), ntheta
-// > 1, rows per wavefront at most FUSE_ROWS, step + 2 <= nsteps.  Makes the
-// drift records of both steps as launch_step does.
-hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, bool fp32, hipStream_t st);
+                       const int *flips, int flip, bool fp32, bool rot, hipStream_t st);
+// Steps s and s + 1 of every solve of the launch in one pass (tiles, bases,
+// step_off, flips and flip as launch_step): reads buffer (s + flip_i) & 1 and
+// writes the other one, so the caller toggles flip_i.  A solve with one step
+// left, or every solve with `single`, takes one step and keeps its parity.
+// Full annulus only (no rotated sector images), ntheta > 1, rows per
+// wavefront at most FUSE_ROWS.  Makes the drift records of the steps it
+// takes as launch_step does.
+hipError_t launch_step2(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases,
+                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, hipStream_t st);
 // Non-equilibrium measures (Sec. II.E) of the state in buffer `cur` into
 // device memory out [NONEQ][nr][nt] float64.
 hipError_t launch_noneq(const SolveDesc &d, int cur, bool fp32, double *out, hipStream_t st);
-// bases[i] += by for i < n.
-hipError_t launch_advance(int64_t *bases, int n, int64_t by, hipStream_t st);
+// bases[i] += by for i < n.  With flips (after `by` steps taken as two-step
+// launches, a single launch closing an odd count): flips[i] toggles when
+// solve i took an odd number of two-step launches, min(left, by) / 2 of them
+// with left = max(nsteps - bases[i], 0).
+hipError_t launch_advance(const SolveDesc *descs, int *flips, int64_t *bases, int n, int64_t by, hipStream_t st);
 // Drift records of steps [base + lo, base + hi) of solves descs[0..n), base =
 // bases[i] (0 if bases is NULL); at most PART_RING steps per call, and the
 // steps must have been launched before on the same stream.

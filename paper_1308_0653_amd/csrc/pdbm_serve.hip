@@ -42,30 +42,38 @@ class Pack {
 
     ~Pack() { destroy(); }
 
-    // Uploads the description, step-base and tile tables of the current
-    // members and drops the captured graph.  Synchronises st.
+    // Uploads the description, step-base, buffer-parity and tile tables of
+    // the current members and drops the captured graph.  The pack steps in
+    // pairs when every member may (Solve::fusable).  Synchronises st.
     int rebuild(hipStream_t st)
     {
         drop_graph();
         rot = false;
+        pairs = !members.empty();
         std::vector<SolveDesc> descs;
         std::vector<uint2> tiles;
         bases_host.clear();
+        flips_host.clear();
         for (size_t i = 0; i < members.size(); ++i) {
             descs.push_back(members[i]->hd);
             bases_host.push_back(members[i]->step);
+            flips_host.push_back(members[i]->flip);
             rot = rot || members[i]->rot();
+            pairs = pairs && members[i]->fusable();
             for (int t = 0; t < members[i]->waves(); ++t) tiles.push_back(make_uint2((unsigned)i, (unsigned)t));
         }
         ntiles = (int)tiles.size();
         int rc = grow((void **)&ddescs, cap_descs, descs.size() * sizeof(SolveDesc));
         if (rc == PDBM_OK) rc = grow((void **)&dtiles, cap_tiles, tiles.size() * sizeof(uint2));
         if (rc == PDBM_OK) rc = grow((void **)&dbases, cap_bases, bases_host.size() * sizeof(int64_t));
+        if (rc == PDBM_OK) rc = grow((void **)&dflips, cap_flips, flips_host.size() * sizeof(int));
         if (rc) return rc;
         if (!descs.empty()) {
             HIPCHK(hipMemcpyAsync(ddescs, descs.data(), descs.size() * sizeof(SolveDesc), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(dbases, bases_host.data(), bases_host.size() * sizeof(int64_t),
                                   hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(dflips, flips_host.data(), flips_host.size() * sizeof(int), hipMemcpyHostToDevice,
+                                  st));
             HIPCHK(hipMemcpyAsync(dtiles, tiles.data(), tiles.size() * sizeof(uint2), hipMemcpyHostToDevice, st));
         }
         HIPCHK(hipStreamSynchronize(st));
@@ -79,20 +87,22 @@ class Pack {
     int run(int64_t steps, int chunk, hipStream_t st)
     {
         if (members.empty() || steps <= 0) return PDBM_OK;
-        const int64_t total = steps;
         if (chunk > 1 && steps >= chunk) {
             if (!exec || graph_steps != chunk) {
                 int rc = capture(chunk, st);
                 if (rc) return rc;
             }
-            for (; steps >= chunk; steps -= chunk) HIPCHK(hipGraphLaunch(exec, st));
+            for (; steps >= chunk; steps -= chunk) {
+                HIPCHK(hipGraphLaunch(exec, st));
+                advance(chunk);
+            }
         }
         while (steps > 0) {
             const int n = (int)std::min<int64_t>(steps, PART_RING);
             HIPCHK(enqueue_steps(n, st));
+            advance(n);
             steps -= n;
         }
-        for (Solve *m : members) m->step = std::min(m->step + total, m->hd.nsteps);
         return PDBM_OK;
     }
 
@@ -102,10 +112,12 @@ class Pack {
         if (ddescs) (void)hipFree(ddescs);
         if (dtiles) (void)hipFree(dtiles);
         if (dbases) (void)hipFree(dbases);
+        if (dflips) (void)hipFree(dflips);
         ddescs = nullptr;
         dtiles = nullptr;
         dbases = nullptr;
-        cap_descs = cap_tiles = cap_bases = 0;
+        dflips = nullptr;
+        cap_descs = cap_tiles = cap_bases = cap_flips = 0;
     }
 
     int tiles() const { return ntiles; }
@@ -115,8 +127,11 @@ class Pack {
     SolveDesc *ddescs = nullptr;
     uint2 *dtiles = nullptr;
     int64_t *dbases = nullptr;  // step of each member at the start of the next chunk
+    int *dflips = nullptr;      // buffer parity of each member (Solve::flip) at that step
+    bool pairs = false;         // two steps per launch
     std::vector<int64_t> bases_host;
-    size_t cap_descs = 0, cap_tiles = 0, cap_bases = 0;
+    std::vector<int> flips_host;
+    size_t cap_descs = 0, cap_tiles = 0, cap_bases = 0, cap_flips = 0;
     int ntiles = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -153,16 +168,36 @@ class Pack {
     }
 
     // n <= PART_RING steps of every member, their drift records, and the
-    // advance of the step bases.
+    // advance of the step bases (and, in pairs, of the buffer parities).  In
+    // pairs, two-step launch i takes steps 2i and 2i + 1 with parity flips ^
+    // (i & 1) (every member still running has taken the i launches before),
+    // and an odd n ends with a launch of single steps.
     hipError_t enqueue_steps(int n, hipStream_t st)
     {
         const int nm = (int)members.size();
         hipError_t e = hipSuccess;
-        for (int i = 0; i < n && e == hipSuccess; ++i)
-            e = launch_step(ddescs, dtiles, ntiles, dbases, i, 0, fp32, rot, st);
+        if (pairs) {
+            for (int i = 0; 2 * i + 1 < n && e == hipSuccess; ++i)
+                e = launch_step2(ddescs, dtiles, ntiles, dbases, 2 * i, dflips, i & 1, false, fp32, st);
+            if (e == hipSuccess && (n & 1))
+                e = launch_step2(ddescs, dtiles, ntiles, dbases, n - 1, dflips, (n / 2) & 1, true, fp32, st);
+        } else {
+            for (int i = 0; i < n && e == hipSuccess; ++i)
+                e = launch_step(ddescs, dtiles, ntiles, dbases, i, dflips, 0, fp32, rot, st);
+        }
         if (e == hipSuccess) e = launch_records(ddescs, nm, dbases, 0, n, st);
-        if (e == hipSuccess) e = launch_advance(dbases, nm, n, st);
+        if (e == hipSuccess) e = launch_advance(ddescs, pairs ? dflips : nullptr, dbases, nm, n, st);
         return e;
+    }
+
+    // Host copy of what the device tables go through in n steps.
+    void advance(int64_t n)
+    {
+        for (Solve *m : members) {
+            const int64_t left = std::max<int64_t>(m->hd.nsteps - m->step, 0);
+            if (pairs) m->flip ^= (int)((std::min(left, n) / 2) & 1);
+            m->step = std::min(m->step + n, m->hd.nsteps);
+        }
     }
 
     void drop_graph()
@@ -175,13 +210,17 @@ class Pack {
     }
 };
 
-int batch_rows()
+// Rows per wavefront of a packed solve: FUSE_ROWS for one that can step in
+// pairs (full annulus, ntheta > 1), ONE_STEP_BATCH_ROWS otherwise;
+// PDBM_BATCH_ROWS overrides both (tuning).
+int batch_rows(const pdbm_params &p)
 {
     static const int env = [] {
         const char *e = std::getenv("PDBM_BATCH_ROWS");
         return e ? std::atoi(e) : 0;
     }();
-    return env > 0 ? env : DEFAULT_BATCH_ROWS;
+    if (env > 0) return env;
+    return p.ntheta > 1 && p.sector == 8 ? FUSE_ROWS : ONE_STEP_BATCH_ROWS;
 }
 
 // Fields [6][nr][ntheta] (host, may be NULL) and drift report of a member.
@@ -241,7 +280,7 @@ int pdbm_batch_create(int32_t n, const pdbm_params *ps, const pdbm_ic *ics, int3
     b->pack.fp32 = ps[0].precision == PDBM_FP32;
     for (int i = 0; i < n && rc == PDBM_OK; ++i) {
         b->solves.emplace_back(new Solve);
-        rc = b->solves.back()->init(ps[i], ics ? ics + i : nullptr, nullptr, 0, batch_rows(), INT64_MAX, b->st);
+        rc = b->solves.back()->init(ps[i], ics ? ics + i : nullptr, nullptr, 0, batch_rows(ps[i]), INT64_MAX, b->st);
         if (rc == PDBM_OK && hipStreamSynchronize(b->st) != hipSuccess) rc = fail(PDBM_EHIP, "initialisation failed");
         b->pack.members.push_back(b->solves.back().get());
     }
@@ -438,7 +477,7 @@ int pdbm_server::admit_and_step(std::vector<Request *> &admitted)
 {
     for (Request *r : admitted) {
         r->solve.reset(new Solve);
-        int rc = r->solve->init(r->p, &r->ic, nullptr, 0, batch_rows(), r->nsteps, st);
+        int rc = r->solve->init(r->p, &r->ic, nullptr, 0, batch_rows(r->p), r->nsteps, st);
         if (rc == PDBM_OK && hipStreamSynchronize(st) != hipSuccess) rc = PDBM_EHIP;
         if (rc) {
             retire(r, rc);
@@ -550,7 +589,7 @@ int pdbm_submit(pdbm_server *s, const pdbm_params *p, const pdbm_ic *ic, int64_t
     r->ic = *ic;
     r->nsteps = nsteps;
     r->flags = flags;
-    r->bytes = layout_of(*p, batch_rows()).total;
+    r->bytes = layout_of(*p, batch_rows(*p)).total;
     if (r->bytes > s->cap) return fail(PDBM_ENOMEM, "request larger than the server's memory cap");
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return fail(PDBM_EINVAL, "server is shutting down");

@@ -8,181 +8,6 @@
 namespace pdbm {
 namespace {
 
-// One row of one strip: moments, F_k(T), f^eq, BGK + chemical term, Cochran
-// lambda, donor-cell fluxes of f and lambda.  fc: row i.  Marching outward
-// (down = false): prev (LDS, this lane's column) holds row i-1 and fn row
-// i+1; marching inward the roles swap.  prev is replaced by row i as it is
-// consumed.  mr[dd] / mt[dd]: which side is upwind for direction dd (its
-// opposite dd+4 takes the other side).
-template <typename real, bool ROT>
-__device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, real (*prev)[64], const real fc[NQ],
-                                           const real fn[NQ], const real hf[2], double hlam, double lbehind,
-                                           double lc, double lahead,
-                                           const bool mr[4], const bool mt[4], const real acr[4], const real ctv[4],
-                                           bool lr_behind, double csx, double csy, double red[5], bool diag)
-{
-    const DescPtr dp = S.dp;
-    // (1)-(3) moments, weights, f^eq polynomial, BGK and chemical factors
-    const Cell<real> C(dp, fc, lc);
-    const real rho = C.rho, e = C.e, ux = C.ux, uy = C.uy, u2 = C.u2, T = C.T;
-    const real beta = C.beta, omega = C.omega, keep = C.keep, Bz = C.Bz;
-    const double Td = C.Td;
-    const real *F = C.F;
-    const EqPoly<real> &EP = C.EP;
-
-    // azimuthal Courant magnitudes of this row (the geometric 1/r term)
-    const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
-    const real kt = (real)(dp->dt_dth / ri);
-    real act[4];
-#pragma unroll
-    for (int dd = 0; dd < 4; ++dd) act[dd] = fabs(ctv[dd]) * kt;
-
-    const bool store = S.useful;
-    const int lane = S.lane;
-    // pair c of this row sits at rowoff + rest plane + c * pb (pb re-derived
-    // per row so the 16 products stay scalar arithmetic inside the loop)
-    const uint32_t rowoff = (uint32_t)ir * S.row_bytes;
-    const uint32_t pb = opaque(S.pair_bytes);
-    const uint32_t pairs = rowoff + S.rest_bytes;
-
-    // rest particle: no streaming
-    // every lane stores, periodic images into their own column of the row
-    // padding (see stage_row)
-    const real rest = rho * F[0] * EP.c0 * (keep + beta * (u2 - (real)2 * T)) + omega * fc[0];
-    bstore(rest, S.fout, S.vos, rowoff);
-
-#pragma unroll
-    for (int k = 1; k <= 4; ++k) {
-        const real v = (real)speed(k);
-        const real rF = rho * F[k];
-        const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
-        const int base = 1 + 8 * (k - 1);
-        // the ring's new values, stored together under one lane mask (in
-        // halves where the rotated sector's per-lane plane offsets already
-        // hold registers)
-        constexpr int G = ROT ? 2 : 4;  // directions dd per store group
-        real o[8];
-#pragma unroll
-        for (int dd = 0; dd < 4; ++dd) {
-            const real z = v * EP.w(dd);
-            real pp, pm;
-            EP.eval(z, pp, pm);
-            const real bz = Bz * z;
-#pragma unroll
-            for (int sgn = 0; sgn < 2; ++sgn) {
-                const int q = base + dd + 4 * sgn;
-                const real x = fc[q];
-                const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * x : rF * pm * (Ak - bz) + omega * x;
-                // upwind neighbours: C >= 0 takes the lower one (Sec. II.C)
-                const real behind = prev[q][lane];
-                prev[q][lane] = x;
-                const bool rb = sgn == 0 ? mr[dd] : !mr[dd];
-                const real nbr = rb ? behind : fn[q];
-                // both shifts and both halo values are taken by every lane
-                // (a DPP read of a lane switched off by a branch would return
-                // 0), then selected; lanes 0 and 63 take the halo columns
-                const real sl = from_left(x), sr = from_right(x);
-                const real hl = halo_left(hf, q), hr = halo_right(hf, q);
-                const real left = lane == 0 ? hl : sl;
-                const real right = lane == 63 ? hr : sr;
-                const bool tl = sgn == 0 ? mt[dd] : !mt[dd];
-                const real nbt = tl ? left : right;
-                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
-            }
-            // lanes holding rotated sector images store into the padding
-            // too (their values are never read)
-            if (dd % G == G - 1) {
-#pragma unroll
-                for (int e = dd + 1 - G; e <= dd; ++e)
-                    bstore2(o[e], o[e + 4], S.fout, S.vos2, pairs + (uint32_t)(4 * (k - 1) + e) * pb);
-            }
-        }
-    }
-
-    // (4) lambda: closed-form Cochran step, then upwind by own-cell u
-    const double uxd = (double)ux, uyd = (double)uy;
-    const double urp = uxd * csx + uyd * csy;
-    const double utp = -uxd * csy + uyd * csx;
-    const double lreac = C.reacted(dp, lc);
-    const double sll = from_left(lc), slr = from_right(lc);
-    const double hll = lane_value(hlam, 0), hlr = lane_value(hlam, 1);
-    const double lleft = lane == 0 ? hll : sll;
-    const double lright = lane == 63 ? hlr : slr;
-    const double lr = (urp >= 0.0) == lr_behind ? lbehind : lahead;
-    const double lt = utp >= 0.0 ? lleft : lright;
-    const double lnew = lreac - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
-    bstore(lnew, S.lout, S.vols, (uint32_t)ir * S.lrow_bytes);
-
-    if (diag && store) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lc, ri * dp->dr * dp->dth, dp->Q);
-}
-
-// Work of one wavefront: strip `strip`, rows [i0, i1), marched outward or,
-// with `down`, inward.  prev: this wavefront's [NQ][64] LDS slots.
-template <typename real, bool ROT>
-__device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
-                                      real (*prev)[64], double red[5], bool diag)
-{
-    const Strip<real, ROT> S(dp, bufs, strip);
-    const int lane = S.lane;
-    const double2 cs = dp->cs[S.pc];
-    const real cth = (real)cs.x, sth = (real)cs.y;
-    // polar components of directions dd = 0..3 at theta_j (dd+4 is the negative):
-    // v_r = v (cos(dd pi/4) cos th + sin(dd pi/4) sin th),
-    // v_theta = v (sin(dd pi/4) cos th - cos(dd pi/4) sin th)
-    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
-    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
-    const real kr = (real)dp->dt_dr;
-    real acr[4];
-    bool mr[4], mt[4];
-#pragma unroll
-    for (int dd = 0; dd < 4; ++dd) {
-        acr[dd] = fabs(crv[dd]) * kr;
-        mr[dd] = (crv[dd] >= (real)0) != down;  // true: the upwind radial neighbour is the row behind
-        mt[dd] = ctv[dd] >= (real)0;            // true: the upwind azimuthal neighbour is lane-1
-    }
-    const int step = down ? -1 : 1;
-    const int first = down ? i1 - 1 : i0;
-    const int count = i1 - i0;
-    // halos of a row are gathered right after its main loads, when the
-    // adjacent strips fetch the same lines (they then hit in L2)
-    real fc[NQ], fn[NQ], fnn[NQ], hc[2], hn[2], hnn[2];
-    double lp, lc, ln, lnn, hlc, hln, hlnn;
-    S.load_row(first, fc, lc);
-    S.load_halo(first, hc, hlc);
-    row_or_ghost(S, first + step, fn, ln, fc, lc);
-    if (count > 1) S.load_halo(first + step, hn, hln);
-    row_or_ghost(S, first - step, fnn, lp, fc, lc);  // the row behind the first
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) prev[q][lane] = fnn[q];
-    int ir = first;
-    for (int n = 0; n < count; ++n, ir += step) {
-        // the second row ahead is the radial neighbour of the next row
-        // computed, if there is one; rows computed are never ghosts
-        if (n + 1 < count) row_or_ghost(S, ir + 2 * step, fnn, lnn, fn, ln);
-        if (n + 2 < count) S.load_halo(ir + 2 * step, hnn, hlnn);
-        update_row<real, ROT>(S, ir, prev, fc, fn, hc, hlc, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, red,
-                              diag);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            fc[q] = fn[q];
-            fn[q] = fnn[q];
-        }
-        hc[0] = hn[0];
-        hc[1] = hn[1];
-        hlc = hln;
-        hn[0] = hnn[0];
-        hn[1] = hnn[1];
-        hln = hlnn;
-        lp = lc;
-        lc = ln;
-        ln = lnn;
-        // Compiler-only barrier: the LDS slots must not be promoted to
-        // registers across iterations (they exist to free those registers).
-        asm volatile("" ::: "memory");
-    }
-}
-
-// Memory plane of velocity q whose direction index is shifted by r.
 __device__ __forceinline__ int shifted_plane(int q, int r)
 {
     return q == 0 ? 0 : 1 + 8 * ((q - 1) / 8) + ((((q - 1) % 8) + r) & 7);
@@ -339,7 +164,8 @@ struct StepOcc {
 template <typename real, bool ROT>
 __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const SolveDesc *descs, const uint2 *tiles,
                                                                        int ntiles, const int64_t *bases,
-                                                                       int64_t step_off, int flip)
+                                                                       int64_t step_off, const int *flips,
+                                                                       int flip)
 {
     const int nb = gridDim.x;
     const int blk = xcd_tile(blockIdx.x, nb);
@@ -357,7 +183,7 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
     const int64_t step = (bases ? bases[solve] : 0) + step_off;
     if (step >= dp->nsteps) return;
     const bool diag = records(dp, step);
-    const int cur = (int)((step + flip) & 1);
+    const int cur = (int)((step + ((flips ? flips[solve] : 0) ^ flip)) & 1);
     const StepBufs bufs{dp->f[cur], dp->f[cur ^ 1], dp->lam[cur], dp->lam[cur ^ 1]};
     __shared__ real prev[BLOCK / 64][NQ][64];
     double red[5] = {0, 0, 0, 0, 0};
@@ -385,10 +211,16 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
     }
 }
 
-__global__ void k_advance(int64_t *bases, int n, int64_t by)
+__global__ void k_advance(const SolveDesc *descs, int *flips, int64_t *bases, int n, int64_t by)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) bases[i] += by;
+    if (i >= n) return;
+    if (flips) {
+        // two-step launches of solve i in these `by` steps: min(left, by) / 2
+        const int64_t left = max(descs[i].nsteps - bases[i], (int64_t)0);
+        flips[i] ^= (int)((min(left, by) / 2) & 1);
+    }
+    bases[i] += by;
 }
 
 // Drift records of the steps [base + lo, base + hi) of each solve, where base
@@ -434,32 +266,32 @@ int solve_waves(int nr, int nt, int rows)
 }
 
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
-                       int flip, bool fp32, bool rot, hipStream_t st)
+                       const int *flips, int flip, bool fp32, bool rot, hipStream_t st)
 {
     const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0) return hipSuccess;
     if (fp32) {
         if (rot)
             hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flip);
+                               step_off, flips, flip);
         else
             hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flip);
+                               step_off, flips, flip);
     } else {
         if (rot)
             hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flip);
+                               step_off, flips, flip);
         else
             hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flip);
+                               step_off, flips, flip);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_advance(int64_t *bases, int n, int64_t by, hipStream_t st)
+hipError_t launch_advance(const SolveDesc *descs, int *flips, int64_t *bases, int n, int64_t by, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, st, bases, n, by);
+    hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, st, descs, flips, bases, n, by);
     return hipGetLastError();
 }
 

@@ -564,21 +564,37 @@ struct DiagOf<float> {
     static constexpr int waves = 2;
 };
 
-// Steps `step` and step + 1 of one solve (descs[0]); tiles as k_step's.  One
-// wavefront per SIMD in float64, where the two steps' rows fill the register
-// file and the LDS rows of four wavefronts most of a CU's LDS; two in
-// float32, whose rows take half the LDS.
+// Steps s and s + 1 of every solve of the launch in one pass over f.  Tiles,
+// step bases and step_off as k_step's (a single solve passes no tile table,
+// so wavefront t takes its tile t, and no bases, so s = step_off).  The state
+// of step s of solve i is in buffer (s + flip_i) & 1 with flip_i = flips[i]
+// ^ flip (flips may be NULL); a two-step launch leaves it in the other
+// buffer, so the caller toggles flip_i after it.  A solve with one step left,
+// or every solve when `single` is set, takes one step instead (the one-step
+// march), which keeps the parity.  One wavefront per SIMD in float64, where
+// the two steps' rows fill the register file and the LDS rows of four
+// wavefronts most of a CU's LDS; two in float32, whose rows take half the
+// LDS.
 template <typename real>
-__global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const SolveDesc *descs, int ntiles,
-                                                                       int64_t step, int flip)
+__global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const SolveDesc *descs, const uint2 *tiles,
+                                                                       int ntiles, const int64_t *bases,
+                                                                       int64_t step_off, const int *flips, int flip,
+                                                                       int single)
 {
     const int nb = gridDim.x;
     const int blk = xcd_tile(blockIdx.x, nb);
     const int t = __builtin_amdgcn_readfirstlane(blk * (BLOCK / 64) + (threadIdx.x >> 6));
     if (t >= ntiles) return;
-    const DescPtr dp = (DescPtr)descs;
-    const bool diagA = records(dp, step), diagB = records(dp, step + 1);
-    const int cur = (int)((step + flip) & 1);
+    int solve = 0, lt = t;
+    if (tiles) {
+        const uint2 e = tiles[t];
+        solve = __builtin_amdgcn_readfirstlane((int)e.x);
+        lt = __builtin_amdgcn_readfirstlane((int)e.y);
+    }
+    const DescPtr dp = (DescPtr)(descs + solve);
+    const int64_t step = (bases ? bases[solve] : 0) + step_off;
+    if (step >= dp->nsteps) return;
+    const int cur = (int)((step + ((flips ? flips[solve] : 0) ^ flip)) & 1);
     const StepBufs bufs{dp->f[cur], dp->f[cur ^ 1], dp->lam[cur], dp->lam[cur ^ 1]};
     __shared__ real fb[BLOCK / 64][16][64];
     __shared__ real gb[BLOCK / 64][16][64];
@@ -589,19 +605,36 @@ __global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const Solv
     __shared__ double hbl[BLOCK / 64][2];
     __shared__ double dacc[BLOCK / 64][2][3];
     const int w = threadIdx.x >> 6;
-    using Diag = typename DiagOf<real>::type;
-    Diag DA(dacc[w][0]), DB(dacc[w][1]);
     const int rows = dp->rows, nstrip = dp->nstrip;
-    const int rb = t / nstrip, strip = t - rb * nstrip;
+    const int rb = lt / nstrip, strip = lt - rb * nstrip;
     const int i0 = rb * rows;
     const int i1 = min(i0 + rows, dp->nr);
+    if (single || step + 1 >= dp->nsteps) {
+        // one step, with the row behind in the LDS row of g
+        const bool diag = records(dp, step);
+        double red[5] = {0, 0, 0, 0, 0};
+        march<real, false>(dp, bufs, strip, i0, i1, (rb & 1) != 0, ga[w], red, diag);
+        if (diag) {
+            const int64_t slot = (step / dp->diag_every) % PART_RING;
+            double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                const double v = wave_sum(red[i]);
+                if ((threadIdx.x & 63) == 0) part[i] = v;
+            }
+        }
+        return;
+    }
+    const bool diagA = records(dp, step), diagB = records(dp, step + 1);
+    using Diag = typename DiagOf<real>::type;
+    Diag DA(dacc[w][0]), DB(dacc[w][1]);
     march2<real>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], DA, DB,
                  diagA, diagB);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         if (!(s == 0 ? diagA : diagB)) continue;
         const int64_t slot = ((step + s) / dp->diag_every) % PART_RING;
-        double *part = dp->wpart + ((size_t)slot * dp->nwaves + t) * 5;
+        double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
             const double v = s == 0 ? DA.total(i) : DB.total(i);
@@ -612,14 +645,17 @@ __global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const Solv
 
 }  // namespace
 
-hipError_t launch_step2(const SolveDesc *descs, int ntiles, int64_t step, int flip, bool fp32, hipStream_t st)
+hipError_t launch_step2(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases,
+                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, hipStream_t st)
 {
     const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0) return hipSuccess;
     if (fp32)
-        hipLaunchKernelGGL(k_step2<float>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
+        hipLaunchKernelGGL(k_step2<float>, dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases, step_off, flips,
+                           flip, (int)single);
     else
-        hipLaunchKernelGGL(k_step2<double>, dim3(nb), dim3(BLOCK), 0, st, descs, ntiles, step, flip);
+        hipLaunchKernelGGL(k_step2<double>, dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases, step_off, flips,
+                           flip, (int)single);
     return hipGetLastError();
 }
 

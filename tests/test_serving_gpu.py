@@ -42,6 +42,13 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
+def _field_errs(F, R):
+    """Normwise error of each of the six fields; the velocity components share
+    the scale max(|u_r|, |u_theta|, sqrt(T)), as u_theta can be near zero."""
+    us = max(np.abs(R[1]).max(), np.abs(R[2]).max(), np.sqrt(np.abs(R[3]).max()))
+    return [np.abs(F[k] - R[k]).max() / (us if k in (1, 2) else max(np.abs(R[k]).max(), 1e-300)) for k in range(6)]
+
+
 @pytest.mark.parametrize("chunk", [0, 7])
 def test_batch_members_match_single_solves_and_oracle(chunk):
     ws = _small_sweep(4, seed=1)
@@ -52,15 +59,16 @@ def test_batch_members_match_single_solves_and_oracle(chunk):
     for i, w in enumerate(ws):
         assert b.step_count(i) == 30
         F, d = b.moments(i)
-        # the solo solve steps one step per launch, as packed members do (its
-        # step(n) would go in pairs, equal to rounding, not bitwise)
+        # packed members and the solo solve both step in pairs, but with
+        # chunks of 7 the pack's pairs and single steps fall elsewhere, and
+        # the row blocks differ: equal to rounding
         solo = P.Solver(params[i], ics[i])
-        for _ in range(30):
-            solo.step(1)
+        solo.step(30)
         Fs, ds = solo.moments()
-        assert np.array_equal(F, Fs), i
+        errs = _field_errs(F, Fs)
+        assert max(errs) <= 1e-12, (i, errs)
         for k in ("mass", "energy", "chem"):
-            assert abs(d[k] - ds[k]) <= 1e-14 * abs(ds[k])
+            assert abs(d[k] - ds[k]) <= 1e-13 * abs(ds[k])
         R = _oracle_fields(w, 30)
         for k in (0, 3, 5):
             assert _rel(F[k], R[k]) < 1e-10, (i, k)
@@ -282,3 +290,33 @@ def test_zero_steps_change_nothing():
         assert np.array_equal(F, F0)
         assert srv.stats()["done"] == 1
         srv.close()
+
+
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_packed_pairs_with_odd_counts(precision):
+    """Packs step in pairs (two steps per launch), with a launch of single
+    steps closing a chunk of odd length and a single step for a member with
+    one step left.  Requests of 31, 24, 17 and 30 steps in chunks of 7 finish
+    inside chunks, and the pack is rebuilt as they leave, so each member's
+    buffer parity is carried across rebuilds.  The results agree with solo
+    solves (pairs from step 0) to rounding and with the oracle."""
+    ws = _small_sweep(4, seed=11)
+    counts = [31, 24, 17, 30]
+    srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=4, chunk_steps=7)
+    ids = [srv.submit(_params(w, precision, diag_every=5), P.make_ic(**w.ic_kw()), n, keep_fields=True)
+           for w, n in zip(ws, counts)]
+    assert srv.wait(60.0)
+    tol = 1e-12 if precision == P.PDBM_FP64 else 1e-5
+    for rid, w, n in zip(ids, ws, counts):
+        state, F, d = srv.poll(rid, fields=True)
+        assert state == P.PDBM_DONE
+        solo = P.Solver(_params(w, precision, diag_every=5), P.make_ic(**w.ic_kw()))
+        solo.step(n)
+        Fs, ds = solo.moments()
+        errs = _field_errs(F, Fs)
+        print(f"n={n} prec={precision}: max rel {max(errs):.2e}", flush=True)
+        assert max(errs) <= tol, (n, errs)
+        R = _oracle_fields(w, n)
+        for k in (0, 3, 5):
+            assert _rel(F[k], R[k]) < (1e-10 if precision == P.PDBM_FP64 else 1e-4), (n, k)
+    srv.close()
