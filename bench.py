@@ -218,13 +218,13 @@ def packed_sweep(P, W, torch, count, nsteps):
 
 def serving_stream(P, W, torch, nreq, packed_rate):
     """Poisson arrivals served by the continuous-batching server (float32,
-    chunks of 25 steps, 200 GB cap), against the plain float64 path running
+    chunks of 24 steps, 200 GB cap), against the plain float64 path running
     the same requests one at a time in arrival order."""
     import threading
     mean_work = W.mean_work_serving()
     rate = 0.8 * packed_rate / mean_work  # offered load 0.8 of the packed throughput
     stream = W.serving_stream(count=nreq, rate=rate)
-    srv = P.Server(hbm_cap_bytes=200 * 10**9, max_slots=64, chunk_steps=25)
+    srv = P.Server(hbm_cap_bytes=200 * 10**9, max_slots=64, chunk_steps=24)
     ids = [None] * len(stream)
     t_start = time.perf_counter()
 
