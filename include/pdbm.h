@@ -266,9 +266,10 @@ int pdbm_batch_noneq(pdbm_batch *b, int32_t i, double *out);
 /* ------------------------------------------------- continuous batching -- */
 /* A request server: submitted solves wait in a first-come-first-served queue
  * and are admitted, between chunks of `chunk_steps` (1 to PDBM_MAX_CHUNK)
- * steps, while fewer than
- * `max_slots` run and the device memory of the running ones (pdbm_state_bytes
- * each) stays within `hbm_cap_bytes`.  All running solves advance together
+ * steps, while fewer than `max_slots` run and the device memory of the
+ * running ones stays within `hbm_cap_bytes` (a packed solve takes its
+ * pdbm_state_bytes up to the drift partial-sum ring, which scales with its
+ * number of wavefronts and so with the packed row blocks).  All running solves advance together
  * in packed, graph-captured launches on the server's stream (NULL: a stream
  * of its own) driven by a scheduler thread; a solve leaves at the chunk
  * boundary after it reaches its step count.  Submit and poll are
