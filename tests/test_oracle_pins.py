@@ -512,6 +512,65 @@ def test_P12_rounding_drift_is_far_below_parity_tolerance():
         assert np.abs(a - b).max() / np.abs(b).max() < 1e-13
 
 
+# ------------------------------------------------------------ drift report
+# The drift report sums cell values times the cell area r_i dr dtheta over the
+# grid (reading R20).  The midpoint rule is exact for the weight r, so for a
+# uniform state each sum is the state's density times the exact area of the
+# annular sector, s pi (r_max^2 - r_min^2) / 8.
+def _sector_area(r_min, r_max, sector):
+    return sector * math.pi / 8.0 * (r_max * r_max - r_min * r_min)
+
+
+@pytest.mark.parametrize("nr,nt,r_min,r_max,sector", [(7, 16, 0.3, 1.0, 8), (5, 9, 0.5, 2.0, 3),
+                                                      (6, 4, 0.0, 0.8, 1)])
+def test_drift_report_of_uniform_states(nr, nt, r_min, r_max, sector):
+    """Uniform states on an annulus, a 3/8 sector and a 1/8 disc: mass
+    rho A, total energy (rho T + rho |u|^2 / 2) A (gamma = 2: internal energy
+    rho T, Sec. II.A), unreleased chemical energy rho Q (1 - lambda) A, and no
+    cell counted as bad."""
+    rho, T, ur, ut, lam, Q = 1.3, 2.1, 0.4, -0.25, 0.35, 0.7
+    s = O.Solver(O.make_params(nr, nt, r_min, r_max, dt=1e-4, tau=2e-4, Q=Q, sector=sector))
+    s.init_ic(0.0, [rho, T, ur, ut, lam], [rho, T, ur, ut, lam])
+    d = s.diag()
+    A = _sector_area(r_min, r_max, sector)
+    for key, want in (("mass", rho * A), ("energy", (rho * T + 0.5 * rho * (ur * ur + ut * ut)) * A),
+                      ("chem", rho * Q * (1.0 - lam) * A)):
+        assert abs(d[key] - want) <= 1e-13 * want, (key, d[key], want)
+    assert d["n_nonfinite"] == 0 and d["n_nonphys"] == 0
+
+
+def test_drift_report_counts_each_bad_cell_once():
+    """Cells made bad through the raw state: a non-finite f, a non-finite
+    lambda, and a non-finite f in a cell of negative density are each one
+    non-finite cell and leave the sums; a cell of negative density (f turned
+    over: rho and the energy change sign, u and T do not) and a cell of zero
+    temperature (all mass at rest) are each one non-physical cell and stay in
+    the sums with their own values."""
+    nr, nt, r_min, r_max, Q = 6, 8, 0.2, 1.0, 0.9
+    rho, T, lam = 1.2, 1.5, 0.25
+    s = O.Solver(O.make_params(nr, nt, r_min, r_max, dt=1e-4, tau=2e-4, Q=Q))
+    s.init_ic(0.0, [rho, T, 0, 0, lam], [rho, T, 0, 0, lam])
+    f, la = s.get_state()
+    dr, dth = (r_max - r_min) / nr, 2 * math.pi / nt
+    w = [(r_min + (i + 0.5) * dr) * dr * dth for i in range(nr)]
+    f[1, 2, :] = np.nan                    # non-finite
+    la[3, 1] = np.nan                      # non-finite
+    f[5, 3, :] *= -1.0
+    f[5, 3, 7] = np.inf                    # non-finite (not also non-physical)
+    f[2, 5, :] *= -1.0                     # rho < 0
+    f[4, 6, :] = 0.0
+    f[4, 6, 0] = rho                       # T = 0
+    s.set_state(f, la)
+    d = s.diag()
+    assert d["n_nonfinite"] == 3 and d["n_nonphys"] == 2, d
+    A = _sector_area(r_min, r_max, 8)
+    gone = w[1] + w[3] + w[5]
+    e, c = rho * T, rho * Q * (1.0 - lam)
+    np.testing.assert_allclose(d["mass"], rho * (A - gone - 2 * w[2]), rtol=1e-13)
+    np.testing.assert_allclose(d["energy"], e * (A - gone - 2 * w[2] - w[4]), rtol=1e-13)
+    np.testing.assert_allclose(d["chem"], c * (A - gone - 2 * w[2]), rtol=1e-13)
+
+
 # ------------------------------------------------------------ initial state
 def test_initial_state_noise_and_regions():
     """Reading of the two-region initial state with +-p_noise uniform noise on
