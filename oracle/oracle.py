@@ -65,6 +65,7 @@ def lib(real: str = "double"):
         L.ora_step.argtypes = [vp, C.c_longlong]
         L.ora_step_count.argtypes = [vp]
         L.ora_step_count.restype = C.c_longlong
+        L.ora_set_tau.argtypes = [vp, C.c_void_p]
         L.ora_fields.argtypes = [vp, dp]
         L.ora_diag.argtypes = [vp, dp, np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")]
         L.ora_weights.argtypes = [C.c_double, dp]
@@ -186,6 +187,15 @@ class Solver:
         f, lam = np.zeros((nr, nt, NQ)), np.zeros((nr, nt))
         self.L.ora_get_state(self.h, f, lam)
         return f, lam
+
+    def set_tau(self, tau):
+        """Per-cell relaxation time [nr][ntheta] (Sec. IV, point (ii)), or
+        None for the parameters' tau in every cell."""
+        if tau is None:
+            self.L.ora_set_tau(self.h, None)
+            return
+        t = np.ascontiguousarray(tau, dtype=np.float64).reshape(self.shape)
+        self.L.ora_set_tau(self.h, t.ctypes.data_as(C.c_void_p))
 
     def step(self, n=1):
         self.L.ora_step(self.h, int(n))

@@ -53,6 +53,11 @@
  *   R17 lambda is not clamped.
  *   R18 If the reaction is gated off or a+b = 0: lambda_reac = lambda.
  *
+ * Per-cell relaxation time (Sec. IV, point (ii)): the paper says tau should
+ * depend on the local state but gives no form, so the oracle takes a field
+ * tau[ir][jt] as an input (ora_set_tau) and relaxes each cell with its own
+ * exp(-dt/tau); without a field every cell uses the parameters' tau.
+ *
  * Parity unpinned: readings R7, R8 and R12.  The tests pin every other part
  * of this file to values the paper or the mathematics fix.  Nothing the
  * paper prints separates these three choices from their alternatives: the
@@ -86,6 +91,7 @@ typedef struct {
     real *f, *fn;     /* [nr][ntheta][NQ] */
     real *lam, *lamn; /* [nr][ntheta]     */
     real *vr, *vt;    /* [ntheta][NQ]: polar velocity components per column */
+    real *tau;        /* [nr][ntheta] per-cell relaxation time, or NULL: p.tau in every cell */
     long long step;
 } ora_state;
 
@@ -186,11 +192,12 @@ static real cochran(real lam, real a, real b, real dt)
     return ((a + b * lam) * E - a * (1 - lam)) / ((a + b * lam) * E + b * (1 - lam));
 }
 
-/* Collision of one cell: BGK relaxation solved analytically over dt plus the
- * chemical term M dt (LB evolution equation of Sec. II.C without the fluxes).
- * Returns moments and reaction coefficients through the out-pointers. */
-static void collide(const ora_params *p, const real f[NQ], real lam, const real vr[NQ], const real vt[NQ], real out[NQ],
-                    real mom[4], real *a_out, real *b_out, int *react)
+/* Collision of one cell: BGK relaxation with the cell's relaxation time tau
+ * solved analytically over dt, plus the chemical term M dt (LB evolution
+ * equation of Sec. II.C without the fluxes).  Returns moments and reaction
+ * coefficients through the out-pointers. */
+static void collide(const ora_params *p, const real f[NQ], real lam, const real vr[NQ], const real vt[NQ], real tau,
+                    real out[NQ], real mom[4], real *a_out, real *b_out, int *react)
 {
     real rho, ur, ut, T;
     moments(f, vr, vt, &rho, &ur, &ut, &T);
@@ -206,7 +213,7 @@ static void collide(const ora_params *p, const real f[NQ], real lam, const real 
         b = (real)p->w2 * ipow(P, p->n);
         R = a * (1 - lam) + b * lam * (1 - lam);
     }
-    real relax = exp(-(real)p->dt / (real)p->tau);
+    real relax = exp(-(real)p->dt / tau);
     for (int q = 0; q < NQ; ++q) {
         real cr = vr[q] - ur, ct = vt[q] - ut;
         /* M_ki = f^eq (-D T + (v-u)^2) / (2 T^2) * (2Q/D) R (Sec. II.B) */
@@ -286,6 +293,7 @@ void ora_destroy(ora_state *s)
     free(s->lamn);
     free(s->vr);
     free(s->vt);
+    free(s->tau);
     free(s);
 }
 
@@ -355,6 +363,20 @@ void ora_get_state(ora_state *s, double *f, double *lam)
 
 long long ora_step_count(ora_state *s) { return s->step; }
 
+/* Per-cell relaxation time field [nr][ntheta] (Sec. IV, point (ii)), or NULL
+ * for the parameters' tau everywhere. */
+void ora_set_tau(ora_state *s, const double *tau)
+{
+    size_t nc = (size_t)s->p.nr * s->p.ntheta;
+    if (!tau) {
+        free(s->tau);
+        s->tau = NULL;
+        return;
+    }
+    if (!s->tau) s->tau = (real *)calloc(nc, sizeof(real));
+    for (size_t i = 0; i < nc; ++i) s->tau[i] = (real)tau[i];
+}
+
 /* One time step of every cell: the LB evolution equation of Sec. II.C with
  * the fluxes f*_r, f*_theta, and the lambda update of Sec. III.A. */
 static void step_once(ora_state *s)
@@ -369,9 +391,10 @@ static void step_once(ora_state *s)
             const real *vr = s->vr + jt * NQ, *vt = s->vt + jt * NQ;
             real *fc = F_AT(s, s->f, ir, jt);
             real lam = s->lam[(size_t)ir * nt + jt];
+            real tau = s->tau ? s->tau[(size_t)ir * nt + jt] : (real)p->tau;
             real coll[NQ], mom[4], a, b;
             int on;
-            collide(p, fc, lam, vr, vt, coll, mom, &a, &b, &on);
+            collide(p, fc, lam, vr, vt, tau, coll, mom, &a, &b, &on);
 
             real *fo = F_AT(s, s->fn, ir, jt);
             for (int q = 0; q < NQ; ++q) {
@@ -564,7 +587,7 @@ void ora_collide(const ora_params *p, const double f[NQ], double lam, double the
     int on;
     velocities((real)theta, vr, vt);
     for (int q = 0; q < NQ; ++q) fr[q] = (real)f[q];
-    collide(p, fr, (real)lam, vr, vt, o, mom, &a, &b, &on);
+    collide(p, fr, (real)lam, vr, vt, (real)p->tau, o, mom, &a, &b, &on);
     for (int q = 0; q < NQ; ++q) out[q] = (double)o[q];
     for (int i = 0; i < 4; ++i) info[i] = (double)mom[i];
     info[4] = (double)a;

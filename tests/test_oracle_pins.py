@@ -637,6 +637,111 @@ def test_P9_steady_detonation_runs_at_cj_speed():
     assert abs(F[5][post, 0] - 1.0) < 1e-3
 
 
+# -------------------------------------- per-cell relaxation time (Sec. IV) --
+# The paper (Sec. IV, point (ii)) says tau should depend on the local state
+# but gives no form; the oracle takes a field tau[ir][jt] as input.
+def _tau_case(seed=11):
+    rng = np.random.default_rng(seed)
+    nr, nt = 6, 8
+    p = O.make_params(nr, nt, 0.3, 1.0, dt=2e-5, tau=5e-5, w1=2.0, w2=3.0, m=1, n=2, Q=1.0, T_th=1.1)
+    s = O.Solver(p)
+    s.init_ic(0.55, [1.5, 20 / 1.5, 0.2, -0.1, 1], [1, 1, 0, 0, 0], 1e-3, 3)
+    f, lam = s.get_state()
+    f = f * (1 + 0.05 * rng.uniform(-1, 1, f.shape))  # off equilibrium everywhere
+    lam = np.clip(lam + 0.1 * rng.uniform(0, 1, lam.shape), 0, 1)
+    tau = rng.uniform(1e-5, 2e-4, (nr, nt))
+    return p, f, lam, tau
+
+
+def test_tau_field_step_is_each_cells_own_uniform_step():
+    """In the unsplit update (reading R8) the fluxes use time-t f, so one
+    step of cell c with a tau field is the step with a uniform tau equal to
+    tau[c]: checked cell by cell, bitwise, on a reacting, moving, off-
+    equilibrium state with a tau field of distinct values (a transposed or
+    shifted index would take another cell's value)."""
+    p, f, lam, tau = _tau_case()
+    nr, nt = p.nr, p.ntheta
+    s = O.Solver(p)
+    s.set_state(f, lam)
+    s.set_tau(tau)
+    s.step(1)
+    gf, gl = s.get_state()
+    for ir in range(nr):
+        for jt in range(nt):
+            q = O.make_params(nr, nt, 0.3, 1.0, dt=p.dt, tau=tau[ir, jt], w1=p.w1, w2=p.w2, m=p.m, n=p.n, Q=p.Q,
+                              T_th=p.T_th)
+            u = O.Solver(q)
+            u.set_state(f, lam)
+            u.step(1)
+            uf, ul = u.get_state()
+            assert np.array_equal(gf[ir, jt], uf[ir, jt]) and gl[ir, jt] == ul[ir, jt], (ir, jt)
+
+
+def test_tau_field_collision_conserves_every_cell():
+    """Whatever tau a cell relaxes with, the collision conserves its mass,
+    momentum and energy (Sec. II.A): one step with the tau field and one with
+    no relaxation at all (tau = inf) differ in every cell by
+    (e^(-dt/tau) - 1)(f - f^eq), whose mass, momentum and energy are zero."""
+    p, f, lam, tau = _tau_case(12)
+    s = O.Solver(p)
+    s.set_state(f, lam)
+    s.set_tau(tau)
+    s.step(1)
+    a, _ = s.get_state()
+    s.set_state(f, lam)
+    s.set_tau(np.full_like(tau, np.inf))
+    s.step(1)
+    b, _ = s.get_state()
+    d = a - b
+    assert np.abs(d).max() > 1e-3 * np.abs(f).max()  # the relaxation did act
+    dth = 2 * np.pi / p.ntheta
+    for jt in range(p.ntheta):
+        vr, vt = O.velocities((jt + 0.5) * dth)
+        for ir in range(p.nr):
+            scale = np.abs(f[ir, jt]).sum()
+            w = np.abs(d[ir, jt]).sum()
+            for mom in (np.ones(33), vr, vt, 0.5 * (vr * vr + vt * vt)):
+                assert abs((d[ir, jt] * mom).sum()) <= 1e-13 * scale * max(1.0, np.abs(mom).max()), (ir, jt)
+            assert w > 0
+
+
+def test_tau_field_pure_relaxation_decays_with_the_cells_own_tau():
+    """A single cell (its radial ghosts and its periodic azimuthal neighbours
+    are itself, so nothing streams) off equilibrium with no reaction: f(n dt)
+    = f^eq + (f0 - f^eq) exp(-n dt / tau_cell) with tau_cell from the field,
+    not the parameters; tau = inf in the field freezes it."""
+    rng = np.random.default_rng(9)
+    p = O.make_params(1, 1, 0.5, 1.0, dt=1e-5, tau=3e-5, w1=0, w2=0, m=1, n=1, Q=0.0, T_th=1.1)
+    feq = O.equilibrium(1.1, 0.0, 0.0, 1.7, np.pi / 4)
+    vr, vt = O.velocities(np.pi / 4)
+    Bm = np.stack([np.ones(33), vr, vt, 0.5 * (vr * vr + vt * vt)])
+    d = feq * 0.03 * rng.uniform(-1, 1, 33)
+    d -= Bm.T @ np.linalg.lstsq(Bm.T, d, rcond=None)[0]
+    f0 = feq + d
+    for tau_cell in (1.2e-5, 8e-5, np.inf):
+        s = O.Solver(p)
+        s.set_state(f0.reshape(1, 1, 33), np.zeros((1, 1)))
+        s.set_tau(np.full((1, 1), tau_cell))
+        s.step(40)
+        f, _ = s.get_state()
+        np.testing.assert_allclose(f[0, 0], feq + d * math.exp(-40 * p.dt / tau_cell), rtol=1e-11, atol=1e-16)
+
+
+def test_tau_field_of_the_uniform_value_changes_nothing():
+    p, f, lam, _ = _tau_case(13)
+    a, b = O.Solver(p), O.Solver(p)
+    for s in (a, b):
+        s.set_state(f, lam)
+    a.set_tau(np.full((p.nr, p.ntheta), p.tau))
+    a.step(5)
+    b.step(5)
+    assert all(np.array_equal(x, y) for x, y in zip(a.get_state(), b.get_state()))
+    a.set_tau(None)  # back to the parameters' tau
+    a.step(3)
+    b.step(3)
+    assert all(np.array_equal(x, y) for x, y in zip(a.get_state(), b.get_state()))
+
+
 # ------------------------------------------------ sector and disc centre --
 def test_sector_halo_equals_full_annulus():
     """Reading of the periodic azimuthal boundary on a sector (Sec. II.D):
