@@ -88,7 +88,10 @@ enum { PDBM_ALLOW_CFL = 1 };                                   /* flags       */
  *   r_min,r_max  0 <= r_min < r_max.  r_min > 0: annulus with zero-gradient
  *                ghost cells at both radial ends.  r_min = 0: disc, whose
  *                centre uses the paper's ghost rule
- *                f(-1, j, k, i) = f(0, j, k, (i+4)%8) (Sec. II.D).
+ *                f(-1, j, k, i) = f(0, j, k, (i+4)%8) (Sec. II.D), the
+ *                image of the cell across the centre; a disc needs sector
+ *                1, 2 or 4, where that image is this rule (PDBM_EINVAL
+ *                otherwise).
  *   dt, tau      time step and BGK relaxation time (> 0; tau may be +inf)
  *   w1, w2       Cochran rate constants (>= 0)
  *   Q            heat release per unit mass (>= 0)

@@ -149,6 +149,13 @@ int pdbm_validate(const pdbm_params *p, const pdbm_ic *ic, double *cfl)
     if (p->flags & ~PDBM_ALLOW_CFL) return fail(PDBM_EINVAL, "unknown flags");
     if (!is_fin(p->r_min) || !is_fin(p->r_max) || p->r_min < 0.0 || !(p->r_max > p->r_min))
         return fail(PDBM_EINVAL, "need 0 <= r_min < r_max");
+    // The disc-centre ghost is the cell's image across the centre, at theta + pi.  The paper's rule
+    // f(-1, j, k, i) = f(0, j, k, (i+4)%8) (Sec. II.D) is that image when the periodic sector divides a
+    // half turn (rotating by the sector angle s pi/4 turns the direction index by s); on any other sector
+    // it would impose a symmetry the solution need not have.
+    if (p->r_min == 0.0 && p->sector != 1 && p->sector != 2 && p->sector != 4)
+        return fail(PDBM_EINVAL, "a disc (r_min = 0) needs sector 1, 2 or 4 (the centre rule takes the image "
+                                 "across the centre, which lies on the grid only when the sector divides a half turn)");
     if (!is_fin(p->dt) || !(p->dt > 0.0)) return fail(PDBM_EINVAL, "dt must be finite and > 0");
     if (std::isnan(p->tau) || !(p->tau > 0.0)) return fail(PDBM_EINVAL, "tau must be > 0");
     if (!is_fin(p->w1) || !is_fin(p->w2) || p->w1 < 0.0 || p->w2 < 0.0)

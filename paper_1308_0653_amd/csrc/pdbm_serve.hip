@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "pdbm_host.h"
+#include "pdbm_ledger.h"
 
 using namespace pdbm;
 
@@ -356,7 +357,6 @@ struct Request {
 }  // namespace
 
 struct pdbm_server {
-    size_t cap = 0;
     int max_slots = 0, chunk = 0;
     hipStream_t st = nullptr;
     bool own_stream = false;
@@ -368,9 +368,8 @@ struct pdbm_server {
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     uint64_t next_id = 1;
-    size_t in_use = 0;
+    Ledger led;  // memory in use, request counts and state moves (guarded by mu)
     bool stop = false;
-    pdbm_server_stats stats{};
     int sched_error = 0;
 
     // scheduler-thread state
@@ -386,6 +385,11 @@ struct pdbm_server {
 
 void pdbm_server::retire(Request *r, int err)
 {
+    {
+        // a request is retired once (the ledger refuses a second time too)
+        std::lock_guard<std::mutex> g(mu);
+        if (r->state != PDBM_RUNNING) return;
+    }
     pdbm_diag d{};
     bool ok = err == 0;
     if (ok && r->solve) {
@@ -402,16 +406,8 @@ void pdbm_server::retire(Request *r, int err)
     }
     std::lock_guard<std::mutex> g(mu);
     r->diag = d;
-    r->state = ok ? PDBM_DONE : PDBM_FAILED;
     r->t_done = now();
-    in_use -= r->bytes;
-    stats.running--;
-    if (ok) {
-        stats.done++;
-        stats.cell_updates += (double)r->p.nr * r->p.ntheta * (double)r->nsteps;
-    } else {
-        stats.failed++;
-    }
+    led.retire(r->state, r->bytes, ok, (double)r->p.nr * r->p.ntheta * (double)r->nsteps);
     done.notify_all();
 }
 
@@ -424,20 +420,16 @@ void pdbm_server::loop()
             for (;;) {
                 while (!queue.empty() && (int)(running.size() + admitted.size()) < max_slots) {
                     Request *r = reqs[queue.front()].get();
-                    if (in_use + r->bytes > cap) break;  // first come, first served
+                    if (!led.fits(r->bytes)) break;  // first come, first served
                     queue.pop_front();
-                    in_use += r->bytes;
-                    r->state = PDBM_RUNNING;
+                    led.admit(r->state, r->bytes);
                     r->t_admit = now();
-                    stats.queued--;
-                    stats.running++;
                     admitted.push_back(r);
                 }
                 if (stop) break;
                 if (!admitted.empty() || !running.empty()) break;
                 cv.wait(lk);
             }
-            stats.hbm_in_use = in_use;
         }
         bool quit;
         {
@@ -447,7 +439,8 @@ void pdbm_server::loop()
         const int rc = quit ? PDBM_OK : admit_and_step(admitted);
         if (quit || rc) {
             // shutting down, or a HIP error left the device state unknown:
-            // every solve still held fails
+            // every solve still held fails (admitted ones whose set-up
+            // failed were retired already and are left alone)
             if (rc) {
                 std::lock_guard<std::mutex> g(mu);
                 sched_error = rc;
@@ -460,11 +453,7 @@ void pdbm_server::loop()
             if (rc) {
                 std::lock_guard<std::mutex> g(mu);
                 stop = true;
-                for (uint64_t id : queue) {
-                    reqs[id]->state = PDBM_FAILED;
-                    stats.queued--;
-                    stats.failed++;
-                }
+                for (uint64_t id : queue) led.drop(reqs[id]->state);
                 queue.clear();
                 done.notify_all();
             }
@@ -501,7 +490,7 @@ int pdbm_server::admit_and_step(std::vector<Request *> &admitted)
     HIPCHK(hipStreamSynchronize(st));
     {
         std::lock_guard<std::mutex> g(mu);
-        stats.steps_launched += chunk;
+        led.stats.steps_launched += chunk;
     }
     std::vector<Request *> still;
     for (size_t i = 0; i < running.size(); ++i) {
@@ -531,11 +520,11 @@ int pdbm_server_create(size_t hbm_cap_bytes, int32_t max_slots, int32_t chunk_st
     if (rc) return rc;
     pdbm_server *s = new (std::nothrow) pdbm_server;
     if (!s) return fail(PDBM_ENOMEM, "host allocation failed");
-    s->cap = hbm_cap_bytes;
+    s->led.cap = hbm_cap_bytes;
     s->max_slots = max_slots;
     s->chunk = chunk_steps;
     s->t0 = Clock::now();
-    s->stats.hbm_cap = hbm_cap_bytes;
+    s->led.stats.hbm_cap = hbm_cap_bytes;
     s->pack[PDBM_FP64].fp32 = false;
     s->pack[PDBM_FP32].fp32 = true;
     if (stream) {
@@ -560,11 +549,7 @@ void pdbm_server_destroy(pdbm_server *s)
         s->stop = true;
         // requests not finished fail: queued ones now, running ones after
         // the chunk in progress
-        for (uint64_t id : s->queue) {
-            s->reqs[id]->state = PDBM_FAILED;
-            s->stats.queued--;
-            s->stats.failed++;
-        }
+        for (uint64_t id : s->queue) s->led.drop(s->reqs[id]->state);
         s->queue.clear();
     }
     s->cv.notify_all();
@@ -590,16 +575,15 @@ int pdbm_submit(pdbm_server *s, const pdbm_params *p, const pdbm_ic *ic, int64_t
     r->nsteps = nsteps;
     r->flags = flags;
     r->bytes = layout_of(*p, batch_rows(*p)).total;
-    if (r->bytes > s->cap) return fail(PDBM_ENOMEM, "request larger than the server's memory cap");
+    if (r->bytes > s->led.cap) return fail(PDBM_ENOMEM, "request larger than the server's memory cap");
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return fail(PDBM_EINVAL, "server is shutting down");
     r->id = s->next_id++;
     r->t_submit = s->now();
     *req_id = r->id;
+    s->led.submit(r->state);
     s->queue.push_back(r->id);
     s->reqs[r->id] = std::move(r);
-    s->stats.queued++;
-    s->stats.submitted++;
     s->cv.notify_all();
     return PDBM_OK;
 }
@@ -650,7 +634,7 @@ int pdbm_server_wait(pdbm_server *s, double timeout_s)
     std::unique_lock<std::mutex> lk(s->mu);
     const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(
                                           timeout_s < 0 ? 1e9 : timeout_s));
-    while (s->stats.queued > 0 || s->stats.running > 0) {
+    while (s->led.stats.queued > 0 || s->led.stats.running > 0) {
         if (s->sched_error) return fail(s->sched_error, "scheduler stopped on an error");
         if (s->done.wait_until(lk, until) == std::cv_status::timeout) return PDBM_EAGAIN;
     }
@@ -661,8 +645,8 @@ int pdbm_server_get_stats(pdbm_server *s, pdbm_server_stats *out)
 {
     if (!s || !out) return fail(PDBM_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> g(s->mu);
-    *out = s->stats;
-    out->hbm_in_use = s->in_use;
+    *out = s->led.stats;
+    out->hbm_in_use = s->led.in_use;
     out->elapsed = s->now();
     return PDBM_OK;
 }

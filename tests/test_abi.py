@@ -149,3 +149,21 @@ def test_empty_batch_is_refused():
     with pytest.raises(P.PdbmError) as e:
         P.Batch([], [])
     assert e.value.code == P.PDBM_EINVAL
+
+
+@pytest.mark.parametrize("sector", range(1, 9))
+def test_disc_needs_a_sector_that_divides_a_half_turn(sector):
+    """The disc-centre ghost of Sec. II.D takes the cell's image across the
+    centre as the same column with directions turned by 4: true on sectors
+    1, 2 and 4, where a half turn is a whole number of periods; any other
+    disc is refused."""
+    p = P.make_params(40, 8, 0.0, 1.0, dt=2e-4, tau=2e-4, w1=1.0, w2=50.0, sector=sector,
+                      flags=P.PDBM_ALLOW_CFL)
+    if sector in (1, 2, 4):
+        P.pdbm_validate(p)
+    else:
+        with pytest.raises(P.PdbmError) as e:
+            P.pdbm_validate(p)
+        assert e.value.code == P.PDBM_EINVAL
+    p.r_min = 0.1  # annuli take every sector
+    P.pdbm_validate(p)

@@ -40,8 +40,8 @@ def _scaled_errors(got, ref, fields):
 
 CASES = {
     "annulus64": W.small_fp64(),
-    "disc": replace(W.small_fp64(), nr=16, ntheta=16, r_min=0.0, r_max=1.0, dt=2e-4, tau=4e-4, r_split=0.3,
-                    nsteps=40),
+    "disc": replace(W.small_fp64(), nr=16, ntheta=8, sector=4, r_min=0.0, r_max=1.0, dt=2e-4, tau=4e-4,
+                    r_split=0.3, nsteps=40),
     "sector3": replace(W.small_fp64(), nr=24, ntheta=24, sector=3, r_min=0.5, dt=1e-4, tau=4e-4, r_split=0.7,
                        nsteps=60),
     "ragged": replace(W.small_fp64(), nr=37, ntheta=71, nsteps=80),

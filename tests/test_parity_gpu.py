@@ -106,10 +106,14 @@ EDGE = {
                        r_split=0.6, nsteps=80),
     "sector3": replace(W.small_fp64(), nr=24, ntheta=24, sector=3, r_min=0.5, dt=1e-4, tau=4e-4,
                        r_split=0.7, nsteps=80),
-    # disc: centre ghost rule, explosion-like initial state (shocked, outward)
-    "disc": W.Workload("disc", 40, 16, 0.0, 1.0, dt=2e-4, tau=2e-4, w1=1.0, w2=50.0, m=1, n=1, Q=1.0, T_th=1.1,
+    # discs: centre ghost rule, explosion-like initial state (shocked,
+    # outward), on a half disc and on the paper's 1/8 sector
+    "disc": W.Workload("disc", 40, 8, 0.0, 1.0, dt=2e-4, tau=2e-4, w1=1.0, w2=50.0, m=1, n=1, Q=1.0, T_th=1.1,
                        r_split=0.3, inner=(1.5, 1.55556, 0.666667, 0.0, 1.0), outer=(1.0, 1.0, 0.0, 0.0, 0.0),
-                       p_noise=1e-6, seed=3, nsteps=100),
+                       p_noise=1e-6, seed=3, nsteps=100, sector=4),
+    "disc_s1": W.Workload("disc_s1", 40, 2, 0.0, 1.0, dt=2e-4, tau=2e-4, w1=1.0, w2=50.0, m=1, n=1, Q=1.0,
+                          T_th=1.1, r_split=0.3, inner=(1.5, 1.55556, 0.666667, 0.0, 1.0),
+                          outer=(1.0, 1.0, 0.0, 0.0, 0.0), p_noise=1e-6, seed=4, nsteps=100, sector=1),
     # a single ring of cells
     "nr1": replace(W.small_fp64(), nr=1, ntheta=64, r_min=0.5, r_max=0.6, r_split=1.0,
                    inner=(1.5, 20 / 1.5, 0.0, 0.0, 0.2), nsteps=50),
