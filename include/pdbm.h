@@ -174,6 +174,30 @@ int pdbm_fk_matrix(double *A);
  * device, PDBM_EHIP. */
 int pdbm_create(const pdbm_params *p, const pdbm_ic *ic, void *workspace, size_t workspace_bytes, void *stream,
                 pdbm_solver **out);
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): pdbm_create without any
+ * allocation, device or host.  The caller's device buffer `state` holds the
+ * solve's state only (two f buffers and two lambda buffers); everything else
+ * a solve keeps on the device (solve description, theta table, drift
+ * partial sums and records, the moments reduction's partials and counter)
+ * lives in a static array of PDBM_SCRATCH_BYTES in the library, one per
+ * device, and the handle itself is that device's static slot.
+ *   state == NULL   *state_bytes receives the bytes the state needs (the
+ *                   parameters are validated; no device is touched)
+ *   state != NULL   at least that many bytes, 256-byte aligned, owned by the
+ *                   caller and never freed by the library
+ * The solver works with every single-solve entry point and ends with
+ * pdbm_destroy, which frees the device's slot.  At most one such solver
+ * exists per device at a time: PDBM_EAGAIN while another holds the slot.
+ * The static array keeps what the previous solver left; everything that must
+ * start at zero is cleared here, on the solver's stream.
+ * Errors: as pdbm_create; PDBM_ENOMEM if the state buffer is too small or
+ * the solve needs more than PDBM_SCRATCH_BYTES of auxiliary memory (about
+ * 2048 x 2048 cells). */
+enum { PDBM_SCRATCH_BYTES = 16 << 20 };
+int pdbm_create_noalloc(const pdbm_params *p, const pdbm_ic *ic, void *state, size_t *state_bytes, void *stream,
+                        pdbm_solver **out);
 void pdbm_destroy(pdbm_solver *s);
 
 /* Sets the state to f = f^eq of host fields [5][nr][ntheta] = (rho, T, u_r,

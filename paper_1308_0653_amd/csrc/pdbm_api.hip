@@ -61,7 +61,9 @@ Layout pdbm::layout_of(const pdbm_params &p, int rows)
     L.hist = align256((size_t)(HIST_CAP + 1) * sizeof(pdbm_diag));
     L.cpart = align256((size_t)L.cblocks * 5 * sizeof(double));
     L.counter = 256;
-    L.total = 2 * L.f + 2 * L.lam + L.cs + L.desc + L.state + L.wpart + L.hist + L.cpart + L.counter;
+    L.state_total = 2 * L.f + 2 * L.lam;
+    L.aux_total = L.cs + L.desc + L.state + L.wpart + L.hist + L.cpart + L.counter;
+    L.total = L.state_total + L.aux_total;
     return L;
 }
 
@@ -235,14 +237,15 @@ int pdbm::check_device()
 }
 
 int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_t bytes, int rows, int64_t nsteps,
-                hipStream_t st)
+                hipStream_t st, char *aux)
 {
     p = pp;
     L = layout_of(p, rows);
     fp32 = p.precision == PDBM_FP32;
     if (workspace) {
-        if (bytes < L.total || ((uintptr_t)workspace & 255))
-            return fail(PDBM_ENOMEM, "workspace smaller than pdbm_state_bytes() or not 256-byte aligned");
+        if (bytes < (aux ? L.state_total : L.total) || ((uintptr_t)workspace & 255))
+            return fail(PDBM_ENOMEM, aux ? "state buffer smaller than its size query or not 256-byte aligned"
+                                         : "workspace smaller than pdbm_state_bytes() or not 256-byte aligned");
         ws = (char *)workspace;
         own = false;
     } else {
@@ -263,6 +266,7 @@ int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_
     hd.f[1] = take(L.f);
     hd.lam[0] = (double *)take(L.lam);
     hd.lam[1] = (double *)take(L.lam);
+    if (aux) q = aux;  // the auxiliary part lives apart from the state
     hd.cs = (const double2 *)take(L.cs);
     dd = (SolveDesc *)take(L.desc);
     hd.state = (SolveState *)take(L.state);
@@ -299,15 +303,21 @@ int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_
     hd.dt = p.dt;
     pdbm_fk_matrix(hd.A);
 
-    // theta table, description, zeroed counters, then the initial state.
-    // Host sources must outlive the copies: the caller synchronises st
+    // theta table (in pieces through a buffer on the stack, each copy
+    // waited for before the buffer is refilled), description, zeroed
+    // counters, then the initial state.  Host sources of the asynchronous
+    // copies (hd, zero_state) must outlive them: the caller synchronises st
     // before returning to its own caller.
-    cs_host.resize(p.ntheta);
     const double dth = hd.dth;
-    for (int j = 0; j < p.ntheta; ++j)
-        cs_host[j] = make_double2(std::cos((j + 0.5) * dth), std::sin((j + 0.5) * dth));
+    double2 piece[256];
+    for (int j0 = 0; j0 < p.ntheta; j0 += 256) {
+        const int n = std::min(256, p.ntheta - j0);
+        for (int j = 0; j < n; ++j)
+            piece[j] = make_double2(std::cos((j0 + j + 0.5) * dth), std::sin((j0 + j + 0.5) * dth));
+        HIPCHK(hipMemcpyAsync((void *)(hd.cs + j0), piece, n * sizeof(double2), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
     zero_state = SolveState{0};
-    HIPCHK(hipMemcpyAsync((void *)hd.cs, cs_host.data(), cs_host.size() * sizeof(double2), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(dd, &hd, sizeof hd, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(hd.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemsetAsync(counter, 0, sizeof(unsigned), st));
@@ -388,11 +398,6 @@ int pdbm::noneq_to_host(const Solve &s, double *out, hipStream_t st)
 }
 
 // ------------------------------------------------------------ one solve ABI --
-struct pdbm_solver {
-    Solve s;
-    hipStream_t st = nullptr;
-};
-
 extern "C" {
 
 int pdbm_create(const pdbm_params *p, const pdbm_ic *ic, void *workspace, size_t workspace_bytes, void *stream,
@@ -423,7 +428,10 @@ void pdbm_destroy(pdbm_solver *h)
     if (!h) return;
     if (h->s.ws) (void)hipStreamSynchronize(h->st);
     h->s.release();
-    delete h;
+    if (h->scratch_dev >= 0)
+        release_scratch_solver(h->scratch_dev);  // the handle is that device's static slot
+    else
+        delete h;
 }
 
 int pdbm_set_fields(pdbm_solver *h, const double *fields)

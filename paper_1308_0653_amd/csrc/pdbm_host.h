@@ -26,9 +26,13 @@ int fail(int code, const std::string &msg);
 // recompute fewer rows with the longest blocks the two-step kernel takes.
 constexpr int ONE_STEP_BATCH_ROWS = 4;
 
-// Device memory of one solve, in this order (all offsets 256-byte aligned).
+// Device memory of one solve, in this order (all offsets 256-byte aligned):
+// the state (two f buffers, two lambda buffers), then the auxiliary part
+// (theta table, description, step state, drift partial sums and records,
+// moments reduction scratch).
 struct Layout {
     size_t f, lam, cs, desc, state, wpart, hist, cpart, counter, total;
+    size_t state_total, aux_total;  // total = state_total + aux_total
     int pitch, rows, nwaves, cblocks;
     size_t esz;
 };
@@ -56,14 +60,17 @@ class Solve {
     int flip = 0;          // the current state is in buffer (step + flip) & 1 (two-step launches toggle it)
     int64_t rec_from = 0;  // drift records are valid from this step on
     int64_t red_to = 0;    // records of steps before this one have been added up
-    std::vector<double2> cs_host;  // staging of uploads (kept until the next sync)
-    SolveState zero_state{};
+    SolveState zero_state{};  // staging of the step-state upload (kept until the next sync)
 
     // Lays out the solve in `workspace` (or a fresh allocation), uploads its
     // description and enqueues its initial state on `st`.  `rows`: rows per
     // wavefront; `nsteps`: step count after which the solve stops advancing.
+    // With `aux`, the workspace holds the state only (L.state_total bytes)
+    // and the auxiliary part goes to `aux` (L.aux_total bytes, 256-byte
+    // aligned).  Allocates device memory only when workspace is NULL and no
+    // host memory at all.
     int init(const pdbm_params &p, const pdbm_ic *ic, void *workspace, size_t bytes, int rows, int64_t nsteps,
-             hipStream_t st);
+             hipStream_t st, char *aux = nullptr);
     void release();  // frees an owned workspace (the stream must be idle)
 
     int cur() const { return (int)((step + flip) & 1); }
@@ -83,4 +90,15 @@ class Solve {
     int moments(double *out, pdbm_diag *diag_dev, hipStream_t st) const;
 };
 
+// Ends a solver made by pdbm_create_noalloc: frees its device's static
+// scratch for the next one (pdbm_noalloc.hip).
+void release_scratch_solver(int dev);
+
 }  // namespace pdbm
+
+// Handle of one solve (the opaque pdbm_solver of the ABI).
+struct pdbm_solver {
+    pdbm::Solve s;
+    hipStream_t st = nullptr;
+    int scratch_dev = -1;  // device whose static scratch holds the auxiliary part (pdbm_create_noalloc), or -1
+};

@@ -20,6 +20,7 @@ PDBM_EAGAIN, PDBM_ENOENT, PDBM_ENONPHYS, PDBM_ENOSYS = -5, -6, -7, -8
 PDBM_FP64, PDBM_FP32 = 0, 1
 PDBM_QUEUED, PDBM_RUNNING, PDBM_DONE, PDBM_FAILED = 0, 1, 2, 3
 PDBM_ALLOW_CFL = 1
+PDBM_SCRATCH_BYTES = 16 << 20
 NQ = 33
 # components of pdbm_noneq's output (Sec. II.E), in order
 NONEQ_NAMES = ("D2_rr", "D2_rt", "D2_tt", "D3_rrr", "D3_rrt", "D3_rtt", "D3_ttt",
@@ -94,6 +95,8 @@ def lib():
             "pdbm_fk_matrix": (C.c_int, [dp]),
             "pdbm_create": (C.c_int, [C.POINTER(pdbm_params), C.POINTER(pdbm_ic), vp, C.c_size_t, vp,
                                       C.POINTER(vp)]),
+            "pdbm_create_noalloc": (C.c_int, [C.POINTER(pdbm_params), C.POINTER(pdbm_ic), vp,
+                                              C.POINTER(C.c_size_t), vp, C.POINTER(vp)]),
             "pdbm_destroy": (None, [vp]),
             "pdbm_set_fields": (C.c_int, [vp, dp]),
             "pdbm_step": (C.c_int, [vp, C.c_int64]),
@@ -187,10 +190,24 @@ def pdbm_create(params: pdbm_params, ic: pdbm_ic | None = None, workspace=None, 
     return Solver(params, ic, workspace=workspace, stream=stream)
 
 
+def pdbm_noalloc_state_bytes(params: pdbm_params) -> int:
+    """Bytes of the state buffer pdbm_create_noalloc needs (its size query)."""
+    n = C.c_size_t(0)
+    _check(lib().pdbm_create_noalloc(C.byref(params), None, None, C.byref(n), None, None))
+    return n.value
+
+
+def pdbm_create_noalloc(params: pdbm_params, ic: pdbm_ic | None, state, stream=None) -> "Solver":
+    """A solve whose state lives in the caller's device tensor `state` and
+    whose other device memory is the library's static scratch."""
+    return Solver(params, ic, workspace=state, stream=stream, noalloc=True)
+
+
 class Solver:
     """Handle of one solve; methods are the pdbm_* calls on it."""
 
-    def __init__(self, params: pdbm_params, ic: pdbm_ic | None = None, workspace=None, stream=None):
+    def __init__(self, params: pdbm_params, ic: pdbm_ic | None = None, workspace=None, stream=None,
+                 noalloc: bool = False):
         self.L = lib()
         self.params = params
         self.nr, self.nt = params.nr, params.ntheta
@@ -201,8 +218,15 @@ class Solver:
             ws_ptr = C.c_void_p(int(workspace.data_ptr()))
             ws_bytes = workspace.numel() * workspace.element_size()
         self.stream = _stream_handle(stream)
-        _check(self.L.pdbm_create(C.byref(params), C.byref(ic) if ic is not None else None, ws_ptr, ws_bytes,
-                                  C.c_void_p(self.stream), C.byref(self.h)))
+        icp = C.byref(ic) if ic is not None else None
+        if noalloc:
+            assert workspace is not None, "pdbm_create_noalloc needs the caller's state buffer"
+            n = C.c_size_t(ws_bytes)
+            _check(self.L.pdbm_create_noalloc(C.byref(params), icp, ws_ptr, C.byref(n), C.c_void_p(self.stream),
+                                              C.byref(self.h)))
+        else:
+            _check(self.L.pdbm_create(C.byref(params), icp, ws_ptr, ws_bytes, C.c_void_p(self.stream),
+                                      C.byref(self.h)))
 
     def close(self):
         if self.h:

@@ -167,3 +167,36 @@ def test_disc_needs_a_sector_that_divides_a_half_turn(sector):
         assert e.value.code == P.PDBM_EINVAL
     p.r_min = 0.1  # annuli take every sector
     P.pdbm_validate(p)
+
+
+def _align256(x):
+    return (x + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("nr,nt,prec", [(64, 64, 0), (37, 130, 1), (500, 1, 0)])
+def test_noalloc_size_query_is_the_state_alone(nr, nt, prec):
+    """pdbm_create_noalloc with no buffer reports the state's bytes: two f
+    buffers of 33 x nr x pitch values and two lambda buffers of nr x pitch
+    doubles (pitch: ntheta rounded up to 64, or 2 for one column), each
+    256-byte aligned; no device is touched."""
+    w = W.small_fp64()
+    p = P.make_params(**{**w.params_kw(), "nr": nr, "ntheta": nt, "r_min": 0.3, "dt": 1e-6}, precision=prec)
+    pitch = 2 if nt == 1 else (nt + 63) // 64 * 64
+    esz = 4 if prec == P.PDBM_FP32 else 8
+    want = 2 * _align256(33 * nr * pitch * esz) + 2 * _align256(nr * pitch * 8)
+    assert P.pdbm_noalloc_state_bytes(p) == want
+    assert want < P.pdbm_state_bytes(p)
+
+
+def test_noalloc_refuses_grids_beyond_the_static_scratch():
+    """The largest float32 grid needs more auxiliary memory (drift partial
+    sums of 16384 wavefronts) than the static scratch holds: a clear
+    PDBM_ENOMEM before any device call."""
+    w = W.small_fp64()
+    p = P.make_params(**{**w.params_kw(), "nr": 4096, "ntheta": 4096, "r_min": 0.3, "dt": 1e-7},
+                      precision=P.PDBM_FP32)
+    n = C.c_size_t(1 << 40)
+    h = C.c_void_p()
+    rc = P.lib().pdbm_create_noalloc(C.byref(p), None, C.c_void_p(1 << 20), C.byref(n), None, C.byref(h))
+    assert rc == P.PDBM_ENOMEM and not h.value
+    assert b"static scratch" in P.lib().pdbm_last_error()
