@@ -67,7 +67,7 @@ enum {
 
 enum { PDBM_FP64 = 0, PDBM_FP32 = 1 };                        /* precision   */
 enum { PDBM_QUEUED = 0, PDBM_RUNNING = 1, PDBM_DONE = 2, PDBM_FAILED = 3 }; /* request */
-enum { PDBM_ALLOW_CFL = 1 };                                   /* flags       */
+enum { PDBM_ALLOW_CFL = 1, PDBM_TAU_FIELD = 2 };               /* flags       */
 
 /* Problem statement of one solve (Sec. II.D and III of the paper).
  *   nr, ntheta   cells in r and theta (>= 1, nr * ntheta <= 2^24, and one
@@ -84,7 +84,9 @@ enum { PDBM_ALLOW_CFL = 1 };                                   /* flags       */
  *                reaction rate, lambda and all reductions stay float64.
  *   m, n         integer pressure exponents of Cochran's rate (>= 0)
  *   diag_every   record the drift diagnostics every this many steps (0: off)
- *   flags        PDBM_ALLOW_CFL skips the Courant-number check
+ *   flags        PDBM_ALLOW_CFL skips the Courant-number check;
+ *                PDBM_TAU_FIELD gives the solve a per-cell relaxation time
+ *                (see pdbm_set_tau; single solves only)
  *   r_min,r_max  0 <= r_min < r_max.  r_min > 0: annulus with zero-gradient
  *                ghost cells at both radial ends.  r_min = 0: disc, whose
  *                centre uses the paper's ghost rule
@@ -92,7 +94,8 @@ enum { PDBM_ALLOW_CFL = 1 };                                   /* flags       */
  *                image of the cell across the centre; a disc needs sector
  *                1, 2 or 4, where that image is this rule (PDBM_EINVAL
  *                otherwise).
- *   dt, tau      time step and BGK relaxation time (> 0; tau may be +inf)
+ *   dt, tau      time step and BGK relaxation time (> 0; tau may be +inf;
+ *                with PDBM_TAU_FIELD, the value every cell starts with)
  *   w1, w2       Cochran rate constants (>= 0)
  *   Q            heat release per unit mass (>= 0)
  *   T_th         ignition temperature: reaction only where T > T_th       */
@@ -203,6 +206,26 @@ void pdbm_destroy(pdbm_solver *s);
 /* Sets the state to f = f^eq of host fields [5][nr][ntheta] = (rho, T, u_r,
  * u_theta, lambda) and the step count to 0.  Synchronous. */
 int pdbm_set_fields(pdbm_solver *s, const double *fields);
+
+/* Per-cell relaxation time.  The paper (Sec. IV, point (ii)) notes that tau
+ * should depend on the local state (density, temperature), and so vary in
+ * space and time, without giving a form; these calls let the caller supply
+ * it.  The solve must have been created with PDBM_TAU_FIELD (PDBM_EINVAL
+ * otherwise); its cells then relax over each step with their own
+ * exp(-dt / tau[i][j]) in place of the parameters' tau, and nothing else
+ * in the step changes.  The field holds until it is set again, so a caller
+ * can update it between calls of pdbm_step.
+ *   pdbm_set_tau        host tau [nr][ntheta] float64, each > 0 (+inf: no
+ *                       relaxation in that cell; PDBM_EINVAL otherwise), or
+ *                       NULL for the parameters' tau everywhere.
+ *                       Synchronous.
+ *   pdbm_set_tau_async  the same from device memory [nr][ntheta] float64,
+ *                       enqueued on the solver's stream; the values are not
+ *                       checked (a value <= 0 or NaN gives non-physical
+ *                       states).  The buffer must stay valid until the
+ *                       stream reaches the call. */
+int pdbm_set_tau(pdbm_solver *s, const double *tau);
+int pdbm_set_tau_async(pdbm_solver *s, const void *tau_device);
 
 /* Enqueues `nsteps` time steps on the solver's stream and returns without
  * waiting.  Every diag_every-th step also records the drift report of the

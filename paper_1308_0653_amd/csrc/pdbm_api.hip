@@ -54,6 +54,7 @@ Layout pdbm::layout_of(const pdbm_params &p, int rows)
     const size_t cells_p = (size_t)p.nr * L.pitch;
     L.f = align256((size_t)NQ * cells_p * L.esz);
     L.lam = align256(cells_p * sizeof(double));
+    L.omega = (p.flags & PDBM_TAU_FIELD) ? align256(cells_p * L.esz) : 0;
     L.cs = align256((size_t)p.ntheta * sizeof(double2));
     L.desc = align256(sizeof(SolveDesc));
     L.state = align256(sizeof(SolveState));
@@ -61,7 +62,7 @@ Layout pdbm::layout_of(const pdbm_params &p, int rows)
     L.hist = align256((size_t)(HIST_CAP + 1) * sizeof(pdbm_diag));
     L.cpart = align256((size_t)L.cblocks * 5 * sizeof(double));
     L.counter = 256;
-    L.state_total = 2 * L.f + 2 * L.lam;
+    L.state_total = 2 * L.f + 2 * L.lam + L.omega;
     L.aux_total = L.cs + L.desc + L.state + L.wpart + L.hist + L.cpart + L.counter;
     L.total = L.state_total + L.aux_total;
     return L;
@@ -148,7 +149,7 @@ int pdbm_validate(const pdbm_params *p, const pdbm_ic *ic, double *cfl)
     if (p->precision != PDBM_FP64 && p->precision != PDBM_FP32) return fail(PDBM_EINVAL, "unknown precision");
     if (p->m < 0 || p->n < 0 || p->m > 64 || p->n > 64) return fail(PDBM_EINVAL, "m, n must be in 0..64");
     if (p->diag_every < 0) return fail(PDBM_EINVAL, "diag_every must be >= 0");
-    if (p->flags & ~PDBM_ALLOW_CFL) return fail(PDBM_EINVAL, "unknown flags");
+    if (p->flags & ~(PDBM_ALLOW_CFL | PDBM_TAU_FIELD)) return fail(PDBM_EINVAL, "unknown flags");
     if (!is_fin(p->r_min) || !is_fin(p->r_max) || p->r_min < 0.0 || !(p->r_max > p->r_min))
         return fail(PDBM_EINVAL, "need 0 <= r_min < r_max");
     // The disc-centre ghost is the cell's image across the centre, at theta + pi.  The paper's rule
@@ -266,6 +267,7 @@ int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_
     hd.f[1] = take(L.f);
     hd.lam[0] = (double *)take(L.lam);
     hd.lam[1] = (double *)take(L.lam);
+    hd.omegaf = L.omega ? (void *)take(L.omega) : nullptr;
     if (aux) q = aux;  // the auxiliary part lives apart from the state
     hd.cs = (const double2 *)take(L.cs);
     dd = (SolveDesc *)take(L.desc);
@@ -331,6 +333,7 @@ int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_
         ic = &uni;
     }
     HIPCHK(launch_init_ic(hd, 0, fp32, *ic, st));
+    if (hd.omegaf) HIPCHK(launch_omega(hd, fp32, nullptr, hd.omega, st));  // every cell starts with the parameters' tau
     step = 0;
     flip = 0;
     rec_from = 0;
@@ -448,6 +451,36 @@ int pdbm_set_fields(pdbm_solver *h, const double *fields)
     return s.set_step(0, h->st);
 }
 
+int pdbm_set_tau(pdbm_solver *h, const double *tau)
+{
+    if (!h) return fail(PDBM_EINVAL, "NULL solver");
+    Solve &s = h->s;
+    if (!s.tauf()) return fail(PDBM_EINVAL, "the solve was created without PDBM_TAU_FIELD");
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (!tau) {
+        HIPCHK(launch_omega(s.hd, s.fp32, nullptr, s.hd.omega, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+        return PDBM_OK;
+    }
+    const size_t n = (size_t)s.p.nr * s.p.ntheta;
+    for (size_t c = 0; c < n; ++c)
+        if (!(tau[c] > 0.0)) return fail(PDBM_EINVAL, "tau must be > 0 (or +inf) in every cell");
+    // the idle f buffer (at least 132 bytes per cell) stages the field
+    double *stage = (double *)s.hd.f[s.cur() ^ 1];
+    HIPCHK(hipMemcpyAsync(stage, tau, n * sizeof(double), hipMemcpyHostToDevice, h->st));
+    HIPCHK(launch_omega(s.hd, s.fp32, stage, 0.0, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return PDBM_OK;
+}
+
+int pdbm_set_tau_async(pdbm_solver *h, const void *tau_device)
+{
+    if (!h || !tau_device) return fail(PDBM_EINVAL, "NULL argument");
+    if (!h->s.tauf()) return fail(PDBM_EINVAL, "the solve was created without PDBM_TAU_FIELD");
+    HIPCHK(launch_omega(h->s.hd, h->s.fp32, (const double *)tau_device, 0.0, h->st));
+    return PDBM_OK;
+}
+
 int pdbm_step(pdbm_solver *h, int64_t nsteps)
 {
     if (!h || nsteps < 0) return fail(PDBM_EINVAL, "bad solver or step count");
@@ -455,12 +488,14 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
     const bool pairs = s.fusable();
     for (int64_t i = 0; i < nsteps;) {
         if (pairs && nsteps - i >= 2) {
-            HIPCHK(launch_step2(s.dd, nullptr, s.waves(), nullptr, s.step, nullptr, s.flip, false, s.fp32, h->st));
+            HIPCHK(launch_step2(s.dd, nullptr, s.waves(), nullptr, s.step, nullptr, s.flip, false, s.fp32, s.tauf(),
+                                h->st));
             s.step += 2;
             s.flip ^= 1;
             i += 2;
         } else {
-            HIPCHK(launch_step(s.dd, nullptr, s.waves(), nullptr, s.step, nullptr, s.flip, s.fp32, s.rot(), h->st));
+            HIPCHK(launch_step(s.dd, nullptr, s.waves(), nullptr, s.step, nullptr, s.flip, s.fp32, s.rot(), s.tauf(),
+                               h->st));
             s.step += 1;
             i += 1;
         }

@@ -1,6 +1,6 @@
 // Kernels off the time-step path: the output moments and drift report
-// (k_moments), the non-equilibrium measures (k_noneq) and the initial
-// state (k_init_ic, k_init_fields).
+// (k_moments), the non-equilibrium measures (k_noneq), the initial state
+// (k_init_ic, k_init_fields) and the per-cell relaxation factors (k_omega).
 #include "pdbm_device.h"
 
 namespace pdbm {
@@ -170,9 +170,33 @@ __global__ __launch_bounds__(BLOCK) void k_init_fields(SolveDesc d, int cur, con
     d.lam[cur][idx] = fields[4 * (size_t)ncell + c];
 }
 
+// ---------------------------------------------- per-cell relaxation time --
+// omegaf[i][j] = exp(-dt / tau[i nt + j]) (tau = +inf gives 1: no
+// relaxation), or `uniform` everywhere when tau is NULL; evaluated in
+// float64, stored in the solve's precision.
+template <typename real>
+__global__ __launch_bounds__(BLOCK) void k_omega(SolveDesc d, const double *tau, double uniform)
+{
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= d.nr * d.nt) return;
+    const int ir = c / d.nt;
+    const int jt = c - ir * d.nt;
+    ((real *)d.omegaf)[(int64_t)ir * d.pitch + jt] = (real)(tau ? exp(-d.dt / tau[c]) : uniform);
+}
+
 }  // namespace
 
 int cell_blocks(int nr, int nt) { return (int)(((int64_t)nr * nt + BLOCK - 1) / BLOCK); }
+
+hipError_t launch_omega(const SolveDesc &d, bool fp32, const double *tau, double uniform, hipStream_t st)
+{
+    const int nb = cell_blocks(d.nr, d.nt);
+    if (fp32)
+        hipLaunchKernelGGL(k_omega<float>, dim3(nb), dim3(BLOCK), 0, st, d, tau, uniform);
+    else
+        hipLaunchKernelGGL(k_omega<double>, dim3(nb), dim3(BLOCK), 0, st, d, tau, uniform);
+    return hipGetLastError();
+}
 
 hipError_t launch_noneq(const SolveDesc &d, int cur, bool fp32, double *out, hipStream_t st)
 {

@@ -515,14 +515,15 @@ struct Cell {
     EqPoly<real> EP;
 
     Cell() = default;
-    __device__ __forceinline__ Cell(DescPtr dp, const real x[NQ], double lc)
+    // om: the cell's relaxation factor exp(-dt/tau)
+    __device__ __forceinline__ Cell(DescPtr dp, const real x[NQ], double lc, real om)
     {
         real jx, jy;
         raw_moments(x, rho, jx, jy, e);
-        init_moments(dp, jx, jy, lc);
+        init_moments(dp, jx, jy, lc, om);
     }
     // from rho, e (members) and the momentum jx, jy
-    __device__ __forceinline__ void init_moments(DescPtr dp, real jx, real jy, double lc)
+    __device__ __forceinline__ void init_moments(DescPtr dp, real jx, real jy, double lc, real om)
     {
         const real irho = (real)1 / rho;
         ux = jx * irho;
@@ -543,7 +544,7 @@ struct Cell {
             R = (1.0 - lc) * (a + b * lc);
         }
         beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
-        omega = (real)dp->omega;
+        omega = om;
         keep = (real)1 - omega;
         Bz = (real)-2 * beta * T;
     }
@@ -562,6 +563,24 @@ struct Cell {
         return lc;
     }
 };
+
+// Relaxation factor exp(-dt/tau) of a cell: the solve's own, or with TAUF
+// the cell's entry of the per-cell field (Sec. IV, point (ii): tau may
+// depend on the local state; the field is the caller's), stored in the
+// solve's precision as [nr][pitch], so that cell (i, j) sits at byte
+// (i pitch + j) sizeof(real) = vo + so as the rest particle's plane does
+// within a row of f.
+template <typename real, bool TAUF>
+__device__ __forceinline__ real omega_at(DescPtr dp, uint32_t vo, uint32_t so)
+{
+    if constexpr (TAUF) {
+        real v;
+        bload(v, rsrc_of(dp->omegaf), vo, so);
+        return v;
+    } else {
+        return (real)dp->omega;
+    }
+}
 
 // Row `row` of the strip into f, or a ghost row outside [0, nr): below r_min
 // the zero-gradient copy of row 0 or the disc-centre rule f(-1, j, k, i) =
@@ -591,7 +610,7 @@ __device__ __forceinline__ void row_or_ghost(const Strip<real, ROT> &S, int row,
 // i+1; marching inward the roles swap.  prev is replaced by row i as it is
 // consumed.  mr[dd] / mt[dd]: which side is upwind for direction dd (its
 // opposite dd+4 takes the other side).
-template <typename real, bool ROT>
+template <typename real, bool ROT, bool TAUF>
 __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, real (*prev)[64], const real fc[NQ],
                                            const real fn[NQ], const real hf[2], double hlam, double lbehind,
                                            double lc, double lahead,
@@ -600,7 +619,7 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
 {
     const DescPtr dp = S.dp;
     // (1)-(3) moments, weights, f^eq polynomial, BGK and chemical factors
-    const Cell<real> C(dp, fc, lc);
+    const Cell<real> C(dp, fc, lc, omega_at<real, TAUF>(dp, S.vo, (uint32_t)ir * S.rest_bytes));
     const real rho = C.rho, e = C.e, ux = C.ux, uy = C.uy, u2 = C.u2, T = C.T;
     const real beta = C.beta, omega = C.omega, keep = C.keep, Bz = C.Bz;
     const double Td = C.Td;
@@ -695,7 +714,7 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
 
 // Work of one wavefront: strip `strip`, rows [i0, i1), marched outward or,
 // with `down`, inward.  prev: this wavefront's [NQ][64] LDS slots.
-template <typename real, bool ROT>
+template <typename real, bool ROT, bool TAUF>
 __device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
                                       real (*prev)[64], double red[5], bool diag)
 {
@@ -737,8 +756,8 @@ __device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int stri
         // computed, if there is one; rows computed are never ghosts
         if (n + 1 < count) row_or_ghost(S, ir + 2 * step, fnn, lnn, fn, ln);
         if (n + 2 < count) S.load_halo(ir + 2 * step, hnn, hlnn);
-        update_row<real, ROT>(S, ir, prev, fc, fn, hc, hlc, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, red,
-                              diag);
+        update_row<real, ROT, TAUF>(S, ir, prev, fc, fn, hc, hlc, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y,
+                                    red, diag);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             fc[q] = fn[q];

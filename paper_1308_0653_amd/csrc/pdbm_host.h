@@ -27,11 +27,12 @@ int fail(int code, const std::string &msg);
 constexpr int ONE_STEP_BATCH_ROWS = 4;
 
 // Device memory of one solve, in this order (all offsets 256-byte aligned):
-// the state (two f buffers, two lambda buffers), then the auxiliary part
+// the state (two f buffers, two lambda buffers, the per-cell relaxation
+// factors of a solve with PDBM_TAU_FIELD), then the auxiliary part
 // (theta table, description, step state, drift partial sums and records,
 // moments reduction scratch).
 struct Layout {
-    size_t f, lam, cs, desc, state, wpart, hist, cpart, counter, total;
+    size_t f, lam, omega, cs, desc, state, wpart, hist, cpart, counter, total;  // omega: per-cell relaxation factors (0 without PDBM_TAU_FIELD)
     size_t state_total, aux_total;  // total = state_total + aux_total
     int pitch, rows, nwaves, cblocks;
     size_t esz;
@@ -80,6 +81,7 @@ class Solve {
     bool fusable() const;
     int waves() const { return L.nwaves; }
     bool rot() const { return p.sector != 8; }
+    bool tauf() const { return hd.omegaf != nullptr; }  // relaxes with a per-cell tau
     // Sets the step count on host and device (stream must be idle).
     int set_step(int64_t s, hipStream_t st);
     // Enqueues the adding up of the drift partial sums of steps [red_to,

@@ -54,9 +54,10 @@ struct SolveDesc {
     int64_t nsteps;   // the solve stops advancing once it has taken this many steps
     double r_min, dr, dth;
     double dt_dr, dt_dth;  // dt/dr, dt/dtheta
-    double omega;          // exp(-dt/tau)
+    double omega;          // exp(-dt/tau) of the parameters' tau
     double w1, w2, Q, T_th, dt;
     double A[16];  // F_k(T) = sum_n A[(k-1)*4+n-1] T^n
+    void *omegaf;  // float or double [nr][pitch] per-cell exp(-dt/tau) (PDBM_TAU_FIELD), else NULL
 };
 
 // Block-level drift reduction of the cell kernels (moments).
@@ -76,7 +77,8 @@ struct DiagCtl {
 // descriptions; `tiles` maps each wavefront tile of the launch to (solve,
 // tile of that solve), or is NULL for a single solve (descs[0], tiles
 // 0..ntiles-1).  All solves share the precision; `rot` selects the variant
-// for sectors other than the full annulus.
+// for sectors other than the full annulus, `tauf` the variant that relaxes
+// each cell with its own exp(-dt/tau) from SolveDesc::omegaf.
 // The step a solve takes is bases[solve] + step_off (bases NULL: step_off);
 // a solve whose step is at or beyond its nsteps is left alone.  A step that
 // makes a drift record leaves partial sums that launch_records adds up.
@@ -84,16 +86,21 @@ struct DiagCtl {
 // flips[i] ^ flip (flips NULL: flip), the parity its two-step launches have
 // left.
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
-                       const int *flips, int flip, bool fp32, bool rot, hipStream_t st);
+                       const int *flips, int flip, bool fp32, bool rot, bool tauf, hipStream_t st);
 // Steps s and s + 1 of every solve of the launch in one pass (tiles, bases,
 // step_off, flips and flip as launch_step): reads buffer (s + flip_i) & 1 and
 // writes the other one, so the caller toggles flip_i.  A solve with one step
 // left, or every solve with `single`, takes one step and keeps its parity.
 // Full annulus only (no rotated sector images), ntheta > 1, rows per
 // wavefront at most FUSE_ROWS.  Makes the drift records of the steps it
-// takes as launch_step does.
+// takes as launch_step does; `tauf` as launch_step.
 hipError_t launch_step2(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases,
-                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, hipStream_t st);
+                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, bool tauf,
+                        hipStream_t st);
+// Per-cell relaxation factors omegaf[i][j] = exp(-dt / tau[i * nt + j]) from
+// a dense float64 tau field in device memory, or all equal to `uniform`
+// with tau NULL; stored in the solve's precision.
+hipError_t launch_omega(const SolveDesc &d, bool fp32, const double *tau, double uniform, hipStream_t st);
 // Non-equilibrium measures (Sec. II.E) of the state in buffer `cur` into
 // device memory out [NONEQ][nr][nt] float64.
 hipError_t launch_noneq(const SolveDesc &d, int cur, bool fp32, double *out, hipStream_t st);

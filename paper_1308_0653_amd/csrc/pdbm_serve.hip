@@ -179,12 +179,12 @@ class Pack {
         hipError_t e = hipSuccess;
         if (pairs) {
             for (int i = 0; 2 * i + 1 < n && e == hipSuccess; ++i)
-                e = launch_step2(ddescs, dtiles, ntiles, dbases, 2 * i, dflips, i & 1, false, fp32, st);
+                e = launch_step2(ddescs, dtiles, ntiles, dbases, 2 * i, dflips, i & 1, false, fp32, false, st);
             if (e == hipSuccess && (n & 1))
-                e = launch_step2(ddescs, dtiles, ntiles, dbases, n - 1, dflips, (n / 2) & 1, true, fp32, st);
+                e = launch_step2(ddescs, dtiles, ntiles, dbases, n - 1, dflips, (n / 2) & 1, true, fp32, false, st);
         } else {
             for (int i = 0; i < n && e == hipSuccess; ++i)
-                e = launch_step(ddescs, dtiles, ntiles, dbases, i, dflips, 0, fp32, rot, st);
+                e = launch_step(ddescs, dtiles, ntiles, dbases, i, dflips, 0, fp32, rot, false, st);
         }
         if (e == hipSuccess) e = launch_records(ddescs, nm, dbases, 0, n, st);
         if (e == hipSuccess) e = launch_advance(ddescs, pairs ? dflips : nullptr, dbases, nm, n, st);
@@ -264,6 +264,7 @@ int pdbm_batch_create(int32_t n, const pdbm_params *ps, const pdbm_ic *ics, int3
         int rc = pdbm_validate(ps + i, ics ? ics + i : nullptr, nullptr);
         if (rc) return rc;
         if (ps[i].precision != ps[0].precision) return fail(PDBM_EINVAL, "all solves of a batch share the precision");
+        if (ps[i].flags & PDBM_TAU_FIELD) return fail(PDBM_EINVAL, "a per-cell tau field is for single solves only");
     }
     int rc = check_device();
     if (rc) return rc;
@@ -568,6 +569,7 @@ int pdbm_submit(pdbm_server *s, const pdbm_params *p, const pdbm_ic *ic, int64_t
     if (!s || !p || !ic || !req_id || nsteps < 0 || (flags & ~PDBM_KEEP_FIELDS)) return fail(PDBM_EINVAL, "bad argument");
     int rc = pdbm_validate(p, ic, nullptr);
     if (rc) return rc;
+    if (p->flags & PDBM_TAU_FIELD) return fail(PDBM_EINVAL, "a per-cell tau field is for single solves only");
     std::unique_ptr<Request> r(new (std::nothrow) Request);
     if (!r) return fail(PDBM_ENOMEM, "host allocation failed");
     r->p = *p;

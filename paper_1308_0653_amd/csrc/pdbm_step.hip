@@ -22,7 +22,7 @@ __device__ __forceinline__ int shifted_plane(int q, int r)
 // sector (periodic halo, f_{k,i}(j-1) = f_{k,(i+s)%8}(j) and f_{k,i}(j+1) =
 // f_{k,(i-s)%8}(j)); they are read back from the wavefront's LDS slot.
 // The arithmetic per cell is that of update_row.
-template <typename real>
+template <typename real, bool TAUF>
 __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, int blk, real (*slot)[64],
                                              double red[5], bool diag)
 {
@@ -66,7 +66,7 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
     bload(hlam, lin, vhl, 0u);
 
     // (1)-(3) moments, weights, f^eq polynomial, BGK and chemical factors
-    const Cell<real> C(dp, fc, lc);
+    const Cell<real> C(dp, fc, lc, omega_at<real, TAUF>(dp, (uint32_t)re * rb, 0u));
     const real rho = C.rho, e = C.e, ux = C.ux, uy = C.uy, u2 = C.u2, T = C.T;
     const real beta = C.beta, omega = C.omega, keep = C.keep, Bz = C.Bz;
     const double Td = C.Td;
@@ -161,7 +161,7 @@ struct StepOcc {
 // strip lt % nstrip.  Each wavefront works on its own: no barriers and no
 // atomics.  A drift-report step leaves per-wavefront partial sums in its
 // slot of the solve's partial-sum ring; k_records adds them up later.
-template <typename real, bool ROT>
+template <typename real, bool ROT, bool TAUF>
 __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const SolveDesc *descs, const uint2 *tiles,
                                                                        int ntiles, const int64_t *bases,
                                                                        int64_t step_off, const int *flips,
@@ -192,13 +192,13 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
     // inward so that the rows bounding two blocks are read by both at once.
     if (dp->nt == 1) {
         // one theta column: lanes along r
-        radial_block<real>(dp, bufs, lt, prev[threadIdx.x >> 6], red, diag);
+        radial_block<real, TAUF>(dp, bufs, lt, prev[threadIdx.x >> 6], red, diag);
     } else {
         const int rows = dp->rows, nstrip = dp->nstrip;
         const int rb = lt / nstrip, strip = lt - rb * nstrip;
         const int i0 = rb * rows;
         const int i1 = min(i0 + rows, dp->nr);
-        march<real, ROT>(dp, bufs, strip, i0, i1, (rb & 1) != 0, prev[threadIdx.x >> 6], red, diag);
+        march<real, ROT, TAUF>(dp, bufs, strip, i0, i1, (rb & 1) != 0, prev[threadIdx.x >> 6], red, diag);
     }
     if (diag) {
         const int64_t slot = (step / dp->diag_every) % PART_RING;
@@ -265,26 +265,28 @@ int solve_waves(int nr, int nt, int rows)
     return (int)((int64_t)((nr + rows - 1) / rows) * ((nt + STRIP - 1) / STRIP));
 }
 
+template <typename real, bool ROT, bool TAUF>
+static void launch_k_step(int nb, hipStream_t st, const SolveDesc *descs, const uint2 *tiles, int ntiles,
+                          const int64_t *bases, int64_t step_off, const int *flips, int flip)
+{
+    hipLaunchKernelGGL((k_step<real, ROT, TAUF>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases, step_off,
+                       flips, flip);
+}
+
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
-                       const int *flips, int flip, bool fp32, bool rot, hipStream_t st)
+                       const int *flips, int flip, bool fp32, bool rot, bool tauf, hipStream_t st)
 {
     const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0) return hipSuccess;
-    if (fp32) {
-        if (rot)
-            hipLaunchKernelGGL((k_step<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flips, flip);
-        else
-            hipLaunchKernelGGL((k_step<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flips, flip);
-    } else {
-        if (rot)
-            hipLaunchKernelGGL((k_step<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flips, flip);
-        else
-            hipLaunchKernelGGL((k_step<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flips, flip);
-    }
+    using L = void (*)(int, hipStream_t, const SolveDesc *, const uint2 *, int, const int64_t *, int64_t, const int *,
+                       int);
+    // [fp32][rot][tauf]
+    static const L table[2][2][2] = {
+        {{launch_k_step<double, false, false>, launch_k_step<double, false, true>},
+         {launch_k_step<double, true, false>, launch_k_step<double, true, true>}},
+        {{launch_k_step<float, false, false>, launch_k_step<float, false, true>},
+         {launch_k_step<float, true, false>, launch_k_step<float, true, true>}}};
+    table[fp32][rot][tauf](nb, st, descs, tiles, ntiles, bases, step_off, flips, flip);
     return hipGetLastError();
 }
 

@@ -131,7 +131,7 @@ struct RowDiag {
 // replaces in `ga` to `gold`, plane by plane, so that the registers of the
 // old row fill as those of fc empty; otherwise it is stored, for the strip's
 // own columns.
-template <typename real, bool STAGEA, class Halo, class Diag>
+template <typename real, bool STAGEA, bool TAUF, class Halo, class Diag>
 __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, real (*behind)[64], const real fc[NQ],
                                           const real *fn, real (*ga)[64], real *gold, const Halo &H, double lbehind,
                                           double lc,
@@ -140,7 +140,7 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
                                           Diag &D, bool diag)
 {
     const DescPtr dp = S.dp;
-    const Cell<real> C(dp, fc, lc);
+    const Cell<real> C(dp, fc, lc, omega_at<real, TAUF>(dp, S.vo, (uint32_t)ir * S.rest_bytes));
     const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
     const real kt = (real)(dp->dt_dth / ri);
     real act[4];
@@ -255,7 +255,7 @@ __device__ __forceinline__ double pair_swap(double v)
 // (right side) takes from there; the first lane of the two keeps lambda.
 // Every lane runs every instruction up to the final stores (the moment
 // exchange is a lane shift).
-template <typename real>
+template <typename real, bool TAUF>
 __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int strip, int i0, int i1,
                                            real (*ef)[FUSE_ROWS][16], double (*el)[FUSE_ROWS])
 {
@@ -333,7 +333,8 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     Cell<real> C;
     C.rho = rho + pair_swap(rho);
     C.e = en + pair_swap(en);
-    C.init_moments(dp, jx + pair_swap(jx), jy + pair_swap(jy), lc);
+    C.init_moments(dp, jx + pair_swap(jx), jy + pair_swap(jy), lc,
+                   omega_at<real, TAUF>(dp, (uint32_t)pc * es + (uint32_t)r * S.rest_bytes, 0u));
 
     const double ri = dp->r_min + ((double)r + 0.5) * dp->dr;
     const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
@@ -413,14 +414,14 @@ __device__ __forceinline__ void fill_behind(real (*behind)[64], const real x[NQ]
 // rows behind of f (fb) and of g (gb), the full row of g just computed (ga),
 // the edge cells (ef, el) and the gathered halo values of stage A's row
 // (hb, hbl).
-template <typename real, class Diag>
+template <typename real, bool TAUF, class Diag>
 __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
                                        real (*fb)[64], real (*gb)[64], real (*ga)[64], real (*ef)[FUSE_ROWS][16],
                                        double (*el)[FUSE_ROWS], real *hb, double *hbl, Diag &DA, Diag &DB,
                                        bool diagA, bool diagB)
 {
     const Strip<real, false> S(dp, bufs, strip);
-    edge_cells<real>(S, strip, i0, i1, ef, el);
+    edge_cells<real, TAUF>(S, strip, i0, i1, ef, el);
     wave_lds_sync();
 
     const int lane = S.lane;
@@ -500,8 +501,8 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
             }
             wave_lds_sync();
             const LdsHalo<real> H{hb, hbl};
-            stage_row<real, true>(S, ir, fb, fc, fn, ga, gc, H, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y, gln,
-                                  DA, diagA && p >= 0 && p < count);
+            stage_row<real, true, TAUF>(S, ir, fb, fc, fn, ga, gc, H, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y,
+                                        gln, DA, diagA && p >= 0 && p < count);
         } else {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) gc[q] = ga[q][lane];
@@ -528,8 +529,8 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
             const int e = ir - step - i0;
             const EdgeHalo<real> H{ef[0][e], ef[1][e], el[0][e], el[1][e]};
             double unused;
-            stage_row<real, false>(S, ir - step, gb, gc, nullptr, ga, nullptr, H, glp, glc, gln, mr, mt, acr, ctv, !down,
-                                   cs.x, cs.y, unused, DB, diagB);
+            stage_row<real, false, TAUF>(S, ir - step, gb, gc, nullptr, ga, nullptr, H, glp, glc, gln, mr, mt, acr, ctv,
+                                         !down, cs.x, cs.y, unused, DB, diagB);
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -575,7 +576,7 @@ struct DiagOf<float> {
 // the two steps' rows fill the register file and the LDS rows of four
 // wavefronts most of a CU's LDS; two in float32, whose rows take half the
 // LDS.
-template <typename real>
+template <typename real, bool TAUF>
 __global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const SolveDesc *descs, const uint2 *tiles,
                                                                        int ntiles, const int64_t *bases,
                                                                        int64_t step_off, const int *flips, int flip,
@@ -613,7 +614,7 @@ __global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const Solv
         // one step, with the row behind in the LDS row of g
         const bool diag = records(dp, step);
         double red[5] = {0, 0, 0, 0, 0};
-        march<real, false>(dp, bufs, strip, i0, i1, (rb & 1) != 0, ga[w], red, diag);
+        march<real, false, TAUF>(dp, bufs, strip, i0, i1, (rb & 1) != 0, ga[w], red, diag);
         if (diag) {
             const int64_t slot = (step / dp->diag_every) % PART_RING;
             double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
@@ -628,8 +629,8 @@ __global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const Solv
     const bool diagA = records(dp, step), diagB = records(dp, step + 1);
     using Diag = typename DiagOf<real>::type;
     Diag DA(dacc[w][0]), DB(dacc[w][1]);
-    march2<real>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], DA, DB,
-                 diagA, diagB);
+    march2<real, TAUF>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], DA,
+                       DB, diagA, diagB);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         if (!(s == 0 ? diagA : diagB)) continue;
@@ -646,16 +647,26 @@ __global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const Solv
 }  // namespace
 
 hipError_t launch_step2(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases,
-                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, hipStream_t st)
+                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, bool tauf,
+                        hipStream_t st)
 {
     const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0) return hipSuccess;
-    if (fp32)
-        hipLaunchKernelGGL(k_step2<float>, dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases, step_off, flips,
-                           flip, (int)single);
-    else
-        hipLaunchKernelGGL(k_step2<double>, dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases, step_off, flips,
-                           flip, (int)single);
+    if (fp32) {
+        if (tauf)
+            hipLaunchKernelGGL((k_step2<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flips, flip, (int)single);
+        else
+            hipLaunchKernelGGL((k_step2<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flips, flip, (int)single);
+    } else {
+        if (tauf)
+            hipLaunchKernelGGL((k_step2<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flips, flip, (int)single);
+        else
+            hipLaunchKernelGGL((k_step2<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flips, flip, (int)single);
+    }
     return hipGetLastError();
 }
 

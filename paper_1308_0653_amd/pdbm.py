@@ -20,6 +20,7 @@ PDBM_EAGAIN, PDBM_ENOENT, PDBM_ENONPHYS, PDBM_ENOSYS = -5, -6, -7, -8
 PDBM_FP64, PDBM_FP32 = 0, 1
 PDBM_QUEUED, PDBM_RUNNING, PDBM_DONE, PDBM_FAILED = 0, 1, 2, 3
 PDBM_ALLOW_CFL = 1
+PDBM_TAU_FIELD = 2
 PDBM_SCRATCH_BYTES = 16 << 20
 NQ = 33
 # components of pdbm_noneq's output (Sec. II.E), in order
@@ -99,6 +100,8 @@ def lib():
                                               C.POINTER(C.c_size_t), vp, C.POINTER(vp)]),
             "pdbm_destroy": (None, [vp]),
             "pdbm_set_fields": (C.c_int, [vp, dp]),
+            "pdbm_set_tau": (C.c_int, [vp, dp]),
+            "pdbm_set_tau_async": (C.c_int, [vp, vp]),
             "pdbm_step": (C.c_int, [vp, C.c_int64]),
             "pdbm_step_count": (C.c_int64, [vp]),
             "pdbm_moments": (C.c_int, [vp, dp, C.POINTER(pdbm_diag)]),
@@ -244,6 +247,26 @@ class Solver:
 
     def __exit__(self, *exc):
         self.close()
+
+    def pdbm_set_tau(self, tau):
+        """Per-cell relaxation time [nr][ntheta] (host array), or None for the
+        parameters' tau everywhere (needs PDBM_TAU_FIELD)."""
+        if tau is None:
+            _check(self.L.pdbm_set_tau(self.h, None))
+            return
+        a = np.ascontiguousarray(tau, dtype=np.float64)
+        assert a.shape == (self.nr, self.nt)
+        _check(self.L.pdbm_set_tau(self.h, _dptr(a)))
+
+    set_tau = pdbm_set_tau
+
+    def pdbm_set_tau_async(self, tau_tensor):
+        """As pdbm_set_tau from a float64 device tensor [nr][ntheta], enqueued
+        on the solver's stream."""
+        assert tau_tensor.is_cuda and tau_tensor.is_contiguous() and tau_tensor.numel() == self.nr * self.nt
+        _check(self.L.pdbm_set_tau_async(self.h, C.c_void_p(int(tau_tensor.data_ptr()))))
+
+    set_tau_async = pdbm_set_tau_async
 
     def pdbm_step(self, nsteps: int = 1):
         _check(self.L.pdbm_step(self.h, int(nsteps)))

@@ -200,3 +200,20 @@ def test_noalloc_refuses_grids_beyond_the_static_scratch():
     rc = P.lib().pdbm_create_noalloc(C.byref(p), None, C.c_void_p(1 << 20), C.byref(n), None, C.byref(h))
     assert rc == P.PDBM_ENOMEM and not h.value
     assert b"static scratch" in P.lib().pdbm_last_error()
+
+
+def test_tau_field_flag_adds_one_field_and_is_for_single_solves():
+    """PDBM_TAU_FIELD (Sec. IV, point (ii): a per-cell relaxation time)
+    passes validation, adds one [nr][pitch] field in the solve's precision
+    to its device memory, and is refused for packed batches before any
+    device call."""
+    w = W.small_fp64()
+    for prec, esz in ((P.PDBM_FP64, 8), (P.PDBM_FP32, 4)):
+        p = P.make_params(**w.params_kw(), precision=prec)
+        q = P.make_params(**w.params_kw(), precision=prec, flags=P.PDBM_TAU_FIELD)
+        P.pdbm_validate(q)
+        assert P.pdbm_state_bytes(q) - P.pdbm_state_bytes(p) == _align256(w.nr * 64 * esz)
+        assert P.pdbm_noalloc_state_bytes(q) - P.pdbm_noalloc_state_bytes(p) == _align256(w.nr * 64 * esz)
+    with pytest.raises(P.PdbmError) as e:
+        P.Batch([P.make_params(**w.params_kw(), flags=P.PDBM_TAU_FIELD)], [P.make_ic(**w.ic_kw())])
+    assert e.value.code == P.PDBM_EINVAL

@@ -67,7 +67,9 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
     instruction and the matching restore."""
     asm = _step_kernels_asm()
     bodies = list(_kernel_bodies(asm, "k_step"))
-    assert len(bodies) == 6  # k_step: 2 precisions x (full annulus, rotated sector); k_step2: 2 precisions
+    # k_step: 2 precisions x (full annulus, rotated sector) x (tau of the solve, per-cell tau); k_step2: 2
+    # precisions x the two kinds of tau
+    assert len(bodies) == 12
     sreg = r"s\[\d+:\d+\]"
     for name, lines in bodies:
         # An exec-narrowing region opens with s_and_saveexec_b64 sX (on every
@@ -116,4 +118,4 @@ def test_step_kernel_uses_no_scratch_memory():
             continue
         seen += 1
         assert int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1)) == 0, name
-    assert seen == 6
+    assert seen == 12
