@@ -19,6 +19,7 @@
 #include <math.h>
 
 #include "pdbm_internal.h"
+#include "pdbm_offsets.h"
 
 namespace pdbm {
 namespace {
@@ -386,59 +387,36 @@ struct Strip {
     int lane, pc, rot;    // physical column, direction shift of this lane's data
     bool useful;
 
-    // memory plane of velocity q for data whose direction index is shifted by r
-    static __device__ __forceinline__ int plane_of(int q, int r)
-    {
-        return q == 0 ? 0 : 1 + 8 * ((q - 1) / 8) + ((((q - 1) % 8) + r) & 7);
-    }
-
     __device__ __forceinline__ Strip(DescPtr dp_, const StepBufs &b, int strip) : dp(dp_)
     {
         fin = rsrc_of(b.f_in);
         fout = rsrc_of(b.f_out);
         lin = rsrc_of(b.lam_in);
         lout = rsrc_of(b.lam_out);
-        const int nt = dp->nt, sec = dp->sector;
         lane = threadIdx.x & 63;
-        const int c0 = strip * STRIP;
-        const int col = c0 + lane;
-        // lanes past the last column hold periodic images of the first ones
-        const int wraps = col / nt;
-        pc = col - wraps * nt;
-        rot = ROT ? ((-wraps * sec) & 7) : 0;
-        useful = col < nt;
-        vo = (uint32_t)pc * (uint32_t)sizeof(real);
-        vo2 = 2u * vo;
-        vol = (uint32_t)pc * 8u;
-        vos = (uint32_t)col * (uint32_t)sizeof(real);
-        vos2 = 2u * vos;
-        vols = (uint32_t)col * 8u;
-        row_bytes = (uint32_t)dp->rstride * (uint32_t)sizeof(real);
-        lrow_bytes = (uint32_t)dp->pitch * 8u;
-        rest_bytes = (uint32_t)dp->plane * (uint32_t)sizeof(real);
-        pair_bytes = 2u * rest_bytes;
+        const RowBytes rb = row_bytes_of(dp->rstride, dp->pitch, (int)sizeof(real));
+        row_bytes = rb.row;
+        lrow_bytes = rb.lrow;
+        rest_bytes = rb.rest;
+        pair_bytes = rb.pair;
+        const StripOffsets o = strip_offsets(dp->nt, dp->pitch, dp->sector, ROT, (int)sizeof(real), rb, strip, lane);
+        pc = o.pc;
+        rot = o.rot;
+        useful = o.useful;
+        vo = o.vo;
+        vo2 = o.vo2;
+        vol = o.vol;
+        vos = o.vos;
+        vos2 = o.vos2;
+        vols = o.vols;
+        vh1 = o.vh1;
+        vh2 = o.vh2;
+        vhl = o.vhl;
 #pragma unroll
         for (int dd = 0; dd < 4; ++dd) {
-            // direction dd of this lane's data is direction (dd + rot) % 8
-            poff[dd] = vo2 + rest_bytes + (uint32_t)((dd + rot) & 3) * pair_bytes;
-            pswap[dd] = ((dd + rot) & 4) != 0;
+            poff[dd] = o.poff[dd];
+            pswap[dd] = o.pswap[dd];
         }
-        // halo columns: c0 - 1 (0 <= c0 < nt) and c0 + 64, as periodic images
-        const int cl = c0 == 0 ? nt - 1 : c0 - 1;
-        const int rl = ROT && c0 == 0 ? (sec & 7) : 0;
-        const int wr = (c0 + STRIP) / nt;
-        const int cr = c0 + STRIP - wr * nt;
-        const int rr = ROT ? ((-wr * sec) & 7) : 0;
-        // gather 1: lanes 0..32 left halo of planes 0..32, lanes 33..63 right
-        // halo of planes 0..30; gather 2: lanes 0, 1 right halo of planes 31,
-        // 32; lambda gather: lane 0 left, lane 1 right (other lanes repeat a
-        // valid address)
-        const int es = (int)sizeof(real);
-        const int64_t pt = dp->pitch;
-        vh1 = lane <= 32 ? (uint32_t)elem_of(plane_of(lane, rl), cl, pt) * es
-                         : (uint32_t)elem_of(plane_of(lane - 33, rr), cr, pt) * es;
-        vh2 = lane < 2 ? (uint32_t)elem_of(plane_of(31 + lane, rr), cr, pt) * es : (uint32_t)cl * es;
-        vhl = lane == 1 ? (uint32_t)cr * 8u : (uint32_t)cl * 8u;
     }
 
     __device__ __forceinline__ void load_row(int row, real f[NQ], double &lam) const
@@ -584,8 +562,10 @@ __device__ __forceinline__ real omega_at(DescPtr dp, uint32_t vo, uint32_t so)
 
 // Row `row` of the strip into f, or a ghost row outside [0, nr): below r_min
 // the zero-gradient copy of row 0 or the disc-centre rule f(-1, j, k, i) =
-// f(0, j, k, (i+4)%8) (Sec. II.D); above r_max the zero-gradient copy of row
-// nr-1.  `edge` holds the boundary row the ghost copies.
+// f(0, j, k, (i+4)%8) (Sec. II.D; discs are sectors 1, 2 or 4, so only the
+// rotated-sector variant meets one at run time); above r_max the
+// zero-gradient copy of row nr-1.  `edge` holds the boundary row the ghost
+// copies.
 template <typename real, bool ROT>
 __device__ __forceinline__ void row_or_ghost(const Strip<real, ROT> &S, int row, real f[NQ], double &lam,
                                              const real edge[NQ], double ledge)
@@ -778,7 +758,6 @@ __device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int stri
     }
 }
 
-// Memory plane of velocity q whose direction index is shifted by r.
 
 // Whether step `s` of a solve makes a drift record.
 __device__ __forceinline__ bool records(DescPtr dp, int64_t s)

@@ -8,11 +8,6 @@
 namespace pdbm {
 namespace {
 
-__device__ __forceinline__ int shifted_plane(int q, int r)
-{
-    return q == 0 ? 0 : 1 + 8 * ((q - 1) / 8) + ((((q - 1) % 8) + r) & 7);
-}
-
 // One step of 64 consecutive rows of a solve with a single theta column
 // (ntheta = 1, the quasi-one-dimensional runs of Sec. III): lane l owns row
 // 64 blk + l.  Radial neighbours come from the adjacent lanes (DPP shifts)
@@ -28,18 +23,18 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
 {
     const int lane = threadIdx.x & 63;
     const int nr = dp->nr, sec = dp->sector;
-    const int r0 = blk * 64;
-    const int row = r0 + lane;
-    const int re = min(row, nr - 1);  // lanes past the last row hold its zero-gradient image
-    const bool store = row < nr;
+    const bool store = blk * 64 + lane < nr;
     const __amdgpu_buffer_rsrc_t fin = rsrc_of(bufs.f_in), fout = rsrc_of(bufs.f_out);
     const __amdgpu_buffer_rsrc_t lin = rsrc_of(bufs.lam_in), lout = rsrc_of(bufs.lam_out);
-    const uint32_t es = (uint32_t)sizeof(real);
-    const uint32_t rowb = (uint32_t)dp->rstride * es;
-    const uint32_t rb = (uint32_t)dp->plane * es, pb = 2u * rb;  // rest plane, one pair (column 0)
-    const int64_t pt = dp->pitch;
-    const uint32_t lrowb = (uint32_t)dp->pitch * 8u;
-    const uint32_t vo = (uint32_t)re * rowb, vol = (uint32_t)re * lrowb;
+    const RowBytes b = row_bytes_of(dp->rstride, dp->pitch, (int)sizeof(real));
+    const uint32_t rb = b.rest, pb = b.pair;  // rest plane, one pair (column 0)
+    // the lane's row, and gathers of the row below the block (ghost of row 0
+    // at r_min: a copy, or at the disc centre row 0 with directions turned
+    // by 4) and of the row above it (clamped: the zero-gradient copy of the
+    // last row)
+    const RadialOffsets o = radial_offsets(nr, dp->pitch, dp->disc, (int)sizeof(real), b, blk, lane);
+    const int re = o.re;
+    const uint32_t vo = o.vo, vol = o.vol;
 
     real fc[NQ];
     double lc;
@@ -48,25 +43,14 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
     for (int c = 0; c < 16; ++c)
         bload2(fc[1 + 8 * (c >> 2) + (c & 3)], fc[5 + 8 * (c >> 2) + (c & 3)], fin, vo, rb + (uint32_t)c * pb);
     bload(lc, lin, vol, 0u);
-    // gathers of the row below the block (ghost of row 0 at r_min: a copy,
-    // or at the disc centre row 0 with directions turned by 4) and of the
-    // row above it (clamped: the zero-gradient copy of the last row)
-    const int rlo = r0 == 0 ? 0 : r0 - 1;
-    const int tlo = r0 == 0 && dp->disc ? 4 : 0;
-    const int rhi = min(r0 + 64, nr - 1);
-    const uint32_t vh1 = lane <= 32 ? (uint32_t)rlo * rowb + (uint32_t)elem_of(shifted_plane(lane, tlo), 0, pt) * es
-                                    : (uint32_t)rhi * rowb + (uint32_t)elem_of(lane - 33, 0, pt) * es;
-    const uint32_t vh2 = lane < 2 ? (uint32_t)rhi * rowb + (uint32_t)elem_of(31 + lane, 0, pt) * es
-                                  : (uint32_t)rlo * rowb;
-    const uint32_t vhl = lane == 1 ? (uint32_t)rhi * lrowb : (uint32_t)rlo * lrowb;
     real hf[2];
     double hlam;
-    bload(hf[0], fin, vh1, 0u);
-    bload(hf[1], fin, vh2, 0u);
-    bload(hlam, lin, vhl, 0u);
+    bload(hf[0], fin, o.vh1, 0u);
+    bload(hf[1], fin, o.vh2, 0u);
+    bload(hlam, lin, o.vhl, 0u);
 
     // (1)-(3) moments, weights, f^eq polynomial, BGK and chemical factors
-    const Cell<real> C(dp, fc, lc, omega_at<real, TAUF>(dp, (uint32_t)re * rb, 0u));
+    const Cell<real> C(dp, fc, lc, omega_at<real, TAUF>(dp, o.om, 0u));
     const real rho = C.rho, e = C.e, ux = C.ux, uy = C.uy, u2 = C.u2, T = C.T;
     const real beta = C.beta, omega = C.omega, keep = C.keep, Bz = C.Bz;
     const double Td = C.Td;

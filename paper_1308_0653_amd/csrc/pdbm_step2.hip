@@ -52,73 +52,19 @@ struct EdgeHalo {
     __device__ __forceinline__ double lright() const { return lr; }
 };
 
-// Sum of x over the wavefront (every lane active), in a fixed order: pairs,
-// quads, half rows and rows of 16 lanes by DPP (after which every lane of a
-// row holds the row's sum), then rows 1 and 3 add rows 0 and 2 by broadcast
-// of lanes 15 and 47, and rows 2 and 3 the first half by broadcast of lane
-// 31.  Lane 63 ends with the total, which is returned to every lane.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_add(double x)
-{
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, false);
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, false);
-    return x + __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double wave_total(double x)
-{
-    x = dpp_add<0xB1, 0xf>(x);   // quad_perm [1, 0, 3, 2]
-    x = dpp_add<0x4E, 0xf>(x);   // quad_perm [2, 3, 0, 1]
-    x = dpp_add<0x141, 0xf>(x);  // row_half_mirror
-    x = dpp_add<0x140, 0xf>(x);  // row_mirror
-    x = dpp_add<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-    x = dpp_add<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 63),
-                            __builtin_amdgcn_readlane(__double2loint(x), 63));
-}
-
 // Drift sums of one step (mass, energy, chemical energy, non-finite and
-// non-physical cells; see diag_cell).  LaneDiag keeps per-lane partial sums
-// over the whole march, added across the wavefront at the end.  RowDiag adds
-// each row across the wavefront at once and keeps the wavefront's running
-// sums in LDS (acc) and its counts in scalar registers, so that no per-lane
-// accumulator stays live through the march: the float32 kernel runs two
-// wavefronts per SIMD and has no registers to spare for them.
+// non-physical cells; see diag_cell), kept per lane over the whole march and
+// added across the wavefront at the end.  In float32 they take 20 of the
+// kernel's 256 registers; summing each row across the wavefront at once
+// instead (a DPP reduction per row, no registers held) took 1.9 % more time.
 struct LaneDiag {
     double red[5] = {0, 0, 0, 0, 0};
-    __device__ __forceinline__ explicit LaneDiag(double *) {}
     __device__ __forceinline__ void add(bool valid, double rho, double ux, double uy, double T, double e, double lam,
                                         double w, double Q)
     {
         if (valid) diag_cell(red, rho, ux, uy, T, e, lam, w, Q);
     }
     __device__ __forceinline__ double total(int i) const { return wave_sum(red[i]); }
-};
-struct RowDiag {
-    double *acc;  // LDS, 3 doubles of this wavefront
-    int nonfinite = 0, nonphys = 0;
-    __device__ __forceinline__ explicit RowDiag(double *a) : acc(a)
-    {
-        acc[0] = acc[1] = acc[2] = 0.0;
-    }
-    // every lane calls this; `valid`: the lane holds a cell of the grid
-    __device__ __forceinline__ void add(bool valid, double rho, double ux, double uy, double T, double e, double lam,
-                                        double w, double Q)
-    {
-        const bool finite = isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy) && isfinite(lam);
-        const bool use = valid && finite;
-        nonfinite += __popcll(__ballot(valid && !finite));
-        nonphys += __popcll(__ballot(use && (rho <= 0.0 || T <= 0.0)));
-        const double m = wave_total(use ? rho * w : 0.0);
-        const double en = wave_total(use ? e * w : 0.0);
-        const double ch = wave_total(use ? rho * Q * (1.0 - lam) * w : 0.0);
-        acc[0] += m;
-        acc[1] += en;
-        acc[2] += ch;
-    }
-    __device__ __forceinline__ double total(int i) const
-    {
-        return i < 3 ? acc[i] : (double)(i == 3 ? nonfinite : nonphys);
-    }
 };
 
 // One row of one of the two steps: the arithmetic of update_row, with the
@@ -264,54 +210,46 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     const int count = i1 - i0;
     const int nr = dp->nr, nt = dp->nt;
     const int r = i0 + min(e, count - 1);  // lanes past the block repeat its last row
-    const int c0 = strip * STRIP;
-    const int pc = side == 0 ? (c0 + nt - 1) % nt : (c0 + STRIP) % nt;
-    const int pl = (pc + nt - 1) % nt, pr = (pc + 1) % nt;
-    const int pk = (side == 0 ? c0 : c0 + STRIP - 1) % nt;  // column of lane 0 / lane 63
-    const double2 cs = dp->cs[pc], ck = dp->cs[pk];
+    const RowBytes rb{S.row_bytes, S.lrow_bytes, S.rest_bytes, S.pair_bytes};
+    // the cell, its radial neighbours (below row 0 the copy of row 0, above
+    // row nr - 1 the copy of row nr - 1: zero-gradient ghosts; the two-step
+    // kernel takes no disc) and its azimuthal neighbours
+    const EdgeOffsets o = edge_offsets(nr, nt, (int)sizeof(real), rb, strip, side, r);
+    const double2 cs = dp->cs[o.pc], ck = dp->cs[o.pk];
     const real cth = (real)cs.x, sth = (real)cs.y;
     const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
     const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
     const real kcth = (real)ck.x, ksth = (real)ck.y;
     const real kctv[4] = {-ksth, (real)SQH * (kcth - ksth), kcth, (real)SQH * (kcth + ksth)};
 
-    const uint32_t es = (uint32_t)sizeof(real), rowb = S.row_bytes, lrowb = S.lrow_bytes;
-    // radial neighbours: below row 0 the copy of row 0 (disc centre: with
-    // directions turned by 4, i.e. the members of each pair swapped), above
-    // row nr - 1 the copy of row nr - 1
-    const int rlo = max(r - 1, 0), rhi = min(r + 1, nr - 1);
-    const bool turn = r == 0 && dp->disc;
-    const uint32_t orow = (uint32_t)r * rowb, olo = (uint32_t)rlo * rowb, ohi = (uint32_t)rhi * rowb;
-    const uint32_t cc = 2u * (uint32_t)pc * es, cl = 2u * (uint32_t)pl * es, cr = 2u * (uint32_t)pr * es;
     // this lane's pairs 8 h .. 8 h + 7 (speeds 2 h + 1, 2 h + 2): directions
     // dd of pair i in x[i], dd + 4 in x[i + 8]
     real x[16], nbr[16], nbt[16], x0;
-    bload(x0, S.fin, orow + (uint32_t)pc * es, 0u);
+    bload(x0, S.fin, o.x0, 0u);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const uint32_t po = S.rest_bytes + (uint32_t)(8 * h + i) * S.pair_bytes;
+        const uint32_t po = pair_in_row(rb, 8 * h + i);
         const int dd = i & 3;
         real lo0, lo1, hi0, hi1, l0, l1, r0, r1;
-        bload2(x[i], x[i + 8], S.fin, orow + cc + po, 0u);
-        bload2(lo0, lo1, S.fin, olo + cc + po, 0u);
-        bload2(hi0, hi1, S.fin, ohi + cc + po, 0u);
-        bload2(l0, l1, S.fin, orow + cl + po, 0u);
-        bload2(r0, r1, S.fin, orow + cr + po, 0u);
-        const real t0 = turn ? lo1 : lo0, t1 = turn ? lo0 : lo1;
+        bload2(x[i], x[i + 8], S.fin, o.orow + o.cc + po, 0u);
+        bload2(lo0, lo1, S.fin, o.olo + o.cc + po, 0u);
+        bload2(hi0, hi1, S.fin, o.ohi + o.cc + po, 0u);
+        bload2(l0, l1, S.fin, o.orow + o.cl + po, 0u);
+        bload2(r0, r1, S.fin, o.orow + o.cr + po, 0u);
         const bool mr = crv[dd] >= (real)0, mt = ctv[dd] >= (real)0;
         // direction dd takes the lower row if mr and the left column if mt,
         // dd + 4 the other ones
-        nbr[i] = mr ? t0 : hi0;
-        nbr[i + 8] = mr ? hi1 : t1;
+        nbr[i] = mr ? lo0 : hi0;
+        nbr[i + 8] = mr ? hi1 : lo1;
         nbt[i] = mt ? l0 : r0;
         nbt[i + 8] = mt ? r1 : l1;
     }
     double lc, lb, la, lL, lR;
-    bload(lc, S.lin, (uint32_t)r * lrowb + (uint32_t)pc * 8u, 0u);
-    bload(lb, S.lin, (uint32_t)rlo * lrowb + (uint32_t)pc * 8u, 0u);
-    bload(la, S.lin, (uint32_t)rhi * lrowb + (uint32_t)pc * 8u, 0u);
-    bload(lL, S.lin, (uint32_t)r * lrowb + (uint32_t)pl * 8u, 0u);
-    bload(lR, S.lin, (uint32_t)r * lrowb + (uint32_t)pr * 8u, 0u);
+    bload(lc, S.lin, o.lc, 0u);
+    bload(lb, S.lin, o.lb, 0u);
+    bload(la, S.lin, o.la, 0u);
+    bload(lL, S.lin, o.lL, 0u);
+    bload(lR, S.lin, o.lR, 0u);
 
     // moments: this lane's two rings (summed as raw_moments does), then the
     // other lane's added
@@ -333,8 +271,7 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     Cell<real> C;
     C.rho = rho + pair_swap(rho);
     C.e = en + pair_swap(en);
-    C.init_moments(dp, jx + pair_swap(jx), jy + pair_swap(jy), lc,
-                   omega_at<real, TAUF>(dp, (uint32_t)pc * es + (uint32_t)r * S.rest_bytes, 0u));
+    C.init_moments(dp, jx + pair_swap(jx), jy + pair_swap(jy), lc, omega_at<real, TAUF>(dp, o.om, 0u));
 
     const double ri = dp->r_min + ((double)r + 0.5) * dp->dr;
     const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
@@ -387,15 +324,6 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Plane q of the ghost row beyond the grid made from row `src`: the copy of
-// the boundary row, with directions turned by 4 below the disc centre.
-__device__ __forceinline__ int ghost_plane(int q, bool turn)
-{
-    if (q == 0 || !turn) return q;
-    const int base = 1 + 8 * ((q - 1) / 8), dir = (q - 1) % 8;
-    return base + ((dir + 4) & 7);
-}
-
 // Fills the compact slots of the row behind (see stage_row) from a full row.
 template <typename real>
 __device__ __forceinline__ void fill_behind(real (*behind)[64], const real x[NQ], const bool mr[4], int lane)
@@ -444,12 +372,12 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
     const int count = i1 - i0;
     const int rbefore = first - step, rafter = first + count * step;  // rows of positions -1 and R
     const bool vlo = rbefore >= 0 && rbefore < nr, vhi = rafter >= 0 && rafter < nr;
-    const bool turn_lo = rbefore < 0 && dp->disc, turn_hi = rafter < 0 && dp->disc;
 
     // f at positions p (fc) and p + 1 (fn) in registers; f(p + 2) is loaded
     // into fc once stage A has used it, and the two swap at the end of the
-    // pass (the loop is not unrolled: one pass is already half the
-    // instruction cache)
+    // pass (the loop is not unrolled: a second copy of the pass, which would
+    // take the swap away, ran slower, 168 against 157 us per float64 launch
+    // and 106 against 103 in float32)
     real fc[NQ], fn[NQ];
     double lp, lc, ln, lx = 0.0;             // lambda of f at positions p-1, p, p+1, p+2
     double glp = 0.0, glc = 0.0, gln = 0.0;  // lambda of g at positions p-2, p-1, p
@@ -504,10 +432,9 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
             stage_row<real, true, TAUF>(S, ir, fb, fc, fn, ga, gc, H, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y,
                                         gln, DA, diagA && p >= 0 && p < count);
         } else {
+            // beyond the last grid row: the zero-gradient ghost of g
 #pragma unroll
             for (int q = 0; q < NQ; ++q) gc[q] = ga[q][lane];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) ga[q][lane] = turn_hi ? gc[ghost_plane(q, true)] : gc[q];
             gln = glc;
         }
         // f at position p + 2 (the row ahead of the next stage A) replaces f(p)
@@ -515,15 +442,13 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
         if (p + 2 < count || (p + 2 == count && vhi)) S.load_halo(ir + 2 * step, hx.h, hx.hl);
         // (B) second step at position p - 1
         if (p == 0 && !vlo) {
-            // the row behind stage B's first row is the ghost of g(0)
+            // the row behind stage B's first row is the (zero-gradient)
+            // ghost of g(0)
 #pragma unroll
             for (int k = 0; k < 4; ++k)
 #pragma unroll
-                for (int dd = 0; dd < 4; ++dd) {
-                    const real a = ga[ghost_plane(1 + 8 * k + dd, turn_lo)][lane];
-                    const real b = ga[ghost_plane(5 + 8 * k + dd, turn_lo)][lane];
-                    gb[4 * k + dd][lane] = mr[dd] ? a : b;
-                }
+                for (int dd = 0; dd < 4; ++dd)
+                    gb[4 * k + dd][lane] = mr[dd] ? ga[1 + 8 * k + dd][lane] : ga[5 + 8 * k + dd][lane];
             glc = gln;
         } else if (p > 0) {
             const int e = ir - step - i0;
@@ -551,18 +476,11 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
     }
 }
 
-// Drift accumulators of the two-step kernel: per lane in float64 (one
-// wavefront per SIMD, with room in the AGPRs), per row in float32 (two
-// wavefronts per SIMD).
+// Wavefronts per SIMD of the two-step kernel: one in float64, whose two
+// steps' rows fill the register file, two in float32.
 template <typename real>
-struct DiagOf {
-    using type = LaneDiag;
-    static constexpr int waves = 1;
-};
-template <>
-struct DiagOf<float> {
-    using type = RowDiag;
-    static constexpr int waves = 2;
+struct Step2Occ {
+    static constexpr int waves = sizeof(real) == 4 ? 2 : 1;
 };
 
 // Steps s and s + 1 of every solve of the launch in one pass over f.  Tiles,
@@ -577,7 +495,7 @@ struct DiagOf<float> {
 // wavefronts most of a CU's LDS; two in float32, whose rows take half the
 // LDS.
 template <typename real, bool TAUF>
-__global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const SolveDesc *descs, const uint2 *tiles,
+__global__ __launch_bounds__(BLOCK, Step2Occ<real>::waves) void k_step2(const SolveDesc *descs, const uint2 *tiles,
                                                                        int ntiles, const int64_t *bases,
                                                                        int64_t step_off, const int *flips, int flip,
                                                                        int single)
@@ -604,7 +522,6 @@ __global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const Solv
     __shared__ double el[BLOCK / 64][2][FUSE_ROWS];
     __shared__ real hb[BLOCK / 64][66];
     __shared__ double hbl[BLOCK / 64][2];
-    __shared__ double dacc[BLOCK / 64][2][3];
     const int w = threadIdx.x >> 6;
     const int rows = dp->rows, nstrip = dp->nstrip;
     const int rb = lt / nstrip, strip = lt - rb * nstrip;
@@ -627,8 +544,7 @@ __global__ __launch_bounds__(BLOCK, DiagOf<real>::waves) void k_step2(const Solv
         return;
     }
     const bool diagA = records(dp, step), diagB = records(dp, step + 1);
-    using Diag = typename DiagOf<real>::type;
-    Diag DA(dacc[w][0]), DB(dacc[w][1]);
+    LaneDiag DA, DB;
     march2<real, TAUF>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], DA,
                        DB, diagA, diagB);
 #pragma unroll

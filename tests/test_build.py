@@ -61,8 +61,8 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
     divergent branch) reads 0 from those lanes, silently corrupting their
     neighbours' update; the source takes every shift unconditionally and
     selects afterwards.  The same holds for the other cross-lane DPP moves
-    (the lane-pair swap of the two-step kernel's edge cells, the wavefront
-    totals of its float32 drift sums).  Checked on the gfx950 assembly: no
+    (the lane-pair swap of the two-step kernel's edge cells).  Checked on the
+    gfx950 assembly: no
     DPP instruction of k_step or k_step2 sits between an exec-narrowing
     instruction and the matching restore."""
     asm = _step_kernels_asm()
