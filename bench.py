@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 PROFILE = os.path.join(ROOT, "profiles", "step_kernels_outward1024.md")
 KERNEL_SOURCES = tuple("paper_1308_0653_amd/csrc/" + f for f in
-                       ("pdbm_device.h", "pdbm_step.hip", "pdbm_step2.hip", "pdbm_internal.h"))
+                       ("pdbm_device.h", "pdbm_step.hip", "pdbm_step2.hip", "pdbm_internal.h", "pdbm_offsets.h"))
 # Algorithmic bytes per cell-update: read and write all 33 f values and lambda.
 BYTES_PER_CELL = {"f64": 33 * 8 * 2 + 8 * 2, "f32": 33 * 4 * 2 + 8 * 2}
 
