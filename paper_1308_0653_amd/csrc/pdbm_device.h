@@ -85,6 +85,16 @@ __device__ __forceinline__ void raw_moments(const real f[NQ], real &rho, real &j
     }
 }
 
+// 1/x: in float32 the hardware reciprocal (within 1 ulp) and one Newton step
+// r + r (1 - x r), three instructions instead of a correctly rounded
+// division's ten, within about half an ulp; in float64 the division.
+__device__ __forceinline__ float inv(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double inv(double x) { return 1.0 / x; }
+
 // Coefficients of the f^eq polynomial in z = v.u / T (Sec. II.B):
 // P(z) = (1 - a + a^2/2) + z (1 - a) + z^2 (1 - a)/2 + z^3/6 + z^4/24, a = u^2/(2T)
 template <typename real>
@@ -93,7 +103,7 @@ struct EqPoly {
     EqPoly() = default;
     __device__ __forceinline__ EqPoly(real ux, real uy, real u2, real T)
     {
-        const real iT = (real)1 / T;
+        const real iT = inv(T);
         const real a = (real)0.5 * u2 * iT;
         c0 = (real)1 - a + (real)0.5 * a * a;
         c1 = (real)1 - a;
@@ -106,16 +116,52 @@ struct EqPoly {
     {
         return d == 0 ? wx : d == 1 ? (real)SQH * (wx + wy) : d == 2 ? wy : (real)SQH * (wy - wx);
     }
-    // P(z) and P(-z) from the even and odd parts
-    __device__ __forceinline__ void eval(real z, real &pp, real &pm) const
+    // the even and odd parts of P: P(z) = ev + od, P(-z) = ev - od
+    __device__ __forceinline__ void parts(real z, real &ev, real &od) const
     {
         const real z2 = z * z;
-        const real ev = c0 + z2 * (c2 + z2 * (real)(1.0 / 24.0));
-        const real od = z * (c1 + z2 * (real)(1.0 / 6.0));
+        ev = c0 + z2 * (c2 + z2 * (real)(1.0 / 24.0));
+        od = z * (c1 + z2 * (real)(1.0 / 6.0));
+    }
+    // P(z) and P(-z)
+    __device__ __forceinline__ void eval(real z, real &pp, real &pm) const
+    {
+        real ev, od;
+        parts(z, ev, od);
         pp = ev + od;
         pm = ev - od;
     }
 };
+
+// One step of an opposite pair of directions (Sec. II.C): direction q,
+// whose velocity projects on u as z = v.u/T, and its opposite (-z).  With
+// f^eq = rho F_k P(+-z), P = ev +- od, and the BGK + chemical factor
+// A_k +- Bz z of the two (A_k = 1 - omega + beta (v^2 + u^2 - 2T),
+// Bz = -2 beta T; Sec. II.B, II.C):
+//   f^coll = rho F_k (ev +- od)(A_k +- Bz z) + omega f = (E +- O) + omega f,
+//   E = rA ev + rb od,  O = rA od + rb ev,  rA = rho F_k A_k,  rb = rho F_k Bz z.
+// The donor-cell fluxes -v acr (f - f_r) - v act (f - f_theta) (|C_r| =
+// v acr, |C_theta| = v act for both directions of the pair) join the f term:
+//   f^new = (E +- O) + s f + v (acr f_r + act f_theta),  s = omega - v (acr + act),
+// with f_r, f_theta the radial and azimuthal upwind neighbours.
+template <typename real>
+__device__ __forceinline__ void pair_coll(const EqPoly<real> &EP, real z, real rA, real rB, real &E, real &O)
+{
+    real ev, od;
+    EP.parts(z, ev, od);
+    const real rb = rB * z;
+    E = ev * rA + od * rb;
+    O = od * rA + ev * rb;
+}
+// f^new of one direction from its collision part c = E +- O.  (acr, act and
+// v enter as they are, not as the products v acr, v act: acr is the same in
+// every row of a strip, and the compiler would keep the sixteen products in
+// registers through the march.)
+template <typename real>
+__device__ __forceinline__ real dir_new(real c, real s, real x, real v, real acr, real act, real nbr, real nbt)
+{
+    return c + s * x + v * (acr * nbr + act * nbt);
+}
 
 template <typename real>
 __device__ __forceinline__ void equilibrium(const double *A, real rho, real ux, real uy, real T, real f[NQ])
@@ -503,7 +549,7 @@ struct Cell {
     // from rho, e (members) and the momentum jx, jy
     __device__ __forceinline__ void init_moments(DescPtr dp, real jx, real jy, double lc, real om)
     {
-        const real irho = (real)1 / rho;
+        const real irho = inv(rho);
         ux = jx * irho;
         uy = jy * irho;
         u2 = ux * ux + uy * uy;
@@ -513,15 +559,15 @@ struct Cell {
         EP = EqPoly<real>(ux, uy, u2, T);
         a = 0.0;
         b = 0.0;
-        double R = 0.0;
+        beta = (real)0;  // no reaction: R = 0
         on = dp->reacts && Td > dp->T_th;
         if (on) {
             const double p = (double)rho * Td;
             a = dp->w1 * ipow(p, dp->m);
             b = dp->w2 * ipow(p, dp->n);
-            R = (1.0 - lc) * (a + b * lc);
+            const double R = (1.0 - lc) * (a + b * lc);
+            beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
         }
-        beta = (real)(dp->Q * R * dp->dt / (2.0 * Td * Td));
         omega = om;
         keep = (real)1 - omega;
         Bz = (real)-2 * beta * T;
@@ -609,9 +655,12 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
     // azimuthal Courant magnitudes of this row (the geometric 1/r term)
     const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
     const real kt = (real)(dp->dt_dth / ri);
-    real act[4];
+    real act[4], aa[4];
 #pragma unroll
-    for (int dd = 0; dd < 4; ++dd) act[dd] = fabs(ctv[dd]) * kt;
+    for (int dd = 0; dd < 4; ++dd) {
+        act[dd] = fabs(ctv[dd]) * kt;
+        aa[dd] = acr[dd] + act[dd];
+    }
 
     const bool store = S.useful;
     const int lane = S.lane;
@@ -631,7 +680,7 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
     for (int k = 1; k <= 4; ++k) {
         const real v = (real)speed(k);
         const real rF = rho * F[k];
-        const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
+        const real rA = rF * (keep + beta * (v * v + u2 - (real)2 * T)), rB = rF * Bz;
         const int base = 1 + 8 * (k - 1);
         // the ring's new values, stored together under one lane mask (in
         // halves where the rotated sector's per-lane plane offsets already
@@ -640,15 +689,13 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
         real o[8];
 #pragma unroll
         for (int dd = 0; dd < 4; ++dd) {
-            const real z = v * EP.w(dd);
-            real pp, pm;
-            EP.eval(z, pp, pm);
-            const real bz = Bz * z;
+            real E, O;
+            pair_coll(EP, v * EP.w(dd), rA, rB, E, O);
+            const real s = omega - v * aa[dd];
 #pragma unroll
             for (int sgn = 0; sgn < 2; ++sgn) {
                 const int q = base + dd + 4 * sgn;
                 const real x = fc[q];
-                const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * x : rF * pm * (Ak - bz) + omega * x;
                 // upwind neighbours: C >= 0 takes the lower one (Sec. II.C)
                 const real behind = prev[q][lane];
                 prev[q][lane] = x;
@@ -663,7 +710,7 @@ __device__ __forceinline__ void update_row(const Strip<real, ROT> &S, int ir, re
                 const real right = lane == 63 ? hr : sr;
                 const bool tl = sgn == 0 ? mt[dd] : !mt[dd];
                 const real nbt = tl ? left : right;
-                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+                o[dd + 4 * sgn] = dir_new(sgn == 0 ? E + O : E - O, s, x, v, acr[dd], act[dd], nbr, nbt);
             }
             // lanes holding rotated sector images store into the padding
             // too (their values are never read)

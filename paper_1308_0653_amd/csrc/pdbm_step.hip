@@ -80,20 +80,18 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
     for (int k = 1; k <= 4; ++k) {
         const real v = (real)speed(k);
         const real rF = rho * F[k];
-        const real Ak = keep + beta * (v * v + u2 - (real)2 * T);
+        const real rA = rF * (keep + beta * (v * v + u2 - (real)2 * T)), rB = rF * Bz;
         const int base = 1 + 8 * (k - 1);
         real o[8];
 #pragma unroll
         for (int dd = 0; dd < 4; ++dd) {
-            const real z = v * EP.w(dd);
-            real pp, pm;
-            EP.eval(z, pp, pm);
-            const real bz = Bz * z;
+            real E, O;
+            pair_coll(EP, v * EP.w(dd), rA, rB, E, O);
+            const real s = omega - v * (acr[dd] + act[dd]);
 #pragma unroll
             for (int sgn = 0; sgn < 2; ++sgn) {
                 const int q = base + dd + 4 * sgn;
                 const real x = fc[q];
-                const real coll = sgn == 0 ? rF * pp * (Ak + bz) + omega * x : rF * pm * (Ak - bz) + omega * x;
                 // radial upwind (C_r >= 0 takes the row below); every lane
                 // takes both shifts, then selects
                 const real sl = from_left(x), sr = from_right(x);
@@ -107,7 +105,7 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
                 const bool left = sgn == 0 ? ctv[dd] >= (real)0 : ctv[dd] < (real)0;
                 const int dir = dd + 4 * sgn;
                 const real nbt = slot[base + ((dir + (left ? sec : 8 - sec)) & 7)][lane];
-                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+                o[dd + 4 * sgn] = dir_new(sgn == 0 ? E + O : E - O, s, x, v, acr[dd], act[dd], nbr, nbt);
             }
         }
         if (store) {

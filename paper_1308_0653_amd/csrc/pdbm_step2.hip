@@ -89,9 +89,12 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
     const Cell<real> C(dp, fc, lc, omega_at<real, TAUF>(dp, S.vo, (uint32_t)ir * S.rest_bytes));
     const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
     const real kt = (real)(dp->dt_dth / ri);
-    real act[4];
+    real act[4], aa[4];
 #pragma unroll
-    for (int dd = 0; dd < 4; ++dd) act[dd] = fabs(ctv[dd]) * kt;
+    for (int dd = 0; dd < 4; ++dd) {
+        act[dd] = fabs(ctv[dd]) * kt;
+        aa[dd] = acr[dd] + act[dd];
+    }
 
     const bool store = S.useful;
     const int lane = S.lane;
@@ -114,15 +117,14 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
     for (int k = 1; k <= 4; ++k) {
         const real v = (real)speed(k);
         const real rF = C.rho * C.F[k];
-        const real Ak = C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T);
+        const real rA = rF * (C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T)), rB = rF * C.Bz;
         const int base = 1 + 8 * (k - 1);
         real o[8];
 #pragma unroll
         for (int dd = 0; dd < 4; ++dd) {
-            const real z = v * C.EP.w(dd);
-            real pp, pm;
-            C.EP.eval(z, pp, pm);
-            const real bz = C.Bz * z;
+            real E, O;
+            pair_coll(C.EP, v * C.EP.w(dd), rA, rB, E, O);
+            const real s = C.omega - v * aa[dd];
             const int c = 4 * (k - 1) + dd;
             const real back = behind[c][lane];
             behind[c][lane] = mr[dd] ? fc[base + dd] : fc[base + dd + 4];
@@ -130,8 +132,6 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
             for (int sgn = 0; sgn < 2; ++sgn) {
                 const int q = base + dd + 4 * sgn;
                 const real x = fc[q];
-                const real coll =
-                    sgn == 0 ? rF * pp * (Ak + bz) + C.omega * x : rF * pm * (Ak - bz) + C.omega * x;
                 const bool rb = sgn == 0 ? mr[dd] : !mr[dd];
                 real ahead;
                 if constexpr (STAGEA)
@@ -145,7 +145,7 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
                 const real right = from_right_or(H.right(q), x);
                 const bool tl = sgn == 0 ? mt[dd] : !mt[dd];
                 const real nbt = tl ? left : right;
-                o[dd + 4 * sgn] = coll - v * (acr[dd] * (x - nbr) + act[dd] * (x - nbt));
+                o[dd + 4 * sgn] = dir_new(sgn == 0 ? E + O : E - O, s, x, v, acr[dd], act[dd], nbr, nbt);
             }
         }
         if (STAGEA) {
@@ -193,12 +193,13 @@ __device__ __forceinline__ double pair_swap(double v)
 // (left) and c0 + 64 (right) as periodic images, for the rows [i0, i1) of the
 // block.  Two lanes take one cell: lane 32 side + 2 e + h takes row i0 + e of
 // its side, h = 0 the speeds 1 and 2 (and the rest particle), h = 1 the
-// speeds 3 and 4.  Each lane gathers its pairs of the cell and of the cell's
-// upwind neighbours (radial ghost rules of Sec. II.D included), one access
-// per pair; the two lanes add up their partial moments, and each updates its
-// pairs as stage A of the strip owning the column does.  Of each opposite
-// pair of directions it keeps the one that lane 0 (left side) or lane 63
-// (right side) takes from there; the first lane of the two keeps lambda.
+// speeds 3 and 4.  Of each opposite pair of directions only the one that
+// lane 0 (left side) or lane 63 (right side) takes from there is kept.  Each
+// lane gathers its pairs of the cell (one access per pair) and, for the kept
+// direction of each, its two upwind neighbours (radial ghost rules of
+// Sec. II.D included); the two lanes add up their partial moments, and each
+// updates its kept directions as stage A of the strip owning the column
+// does.  The first lane of the two keeps lambda.
 // Every lane runs every instruction up to the final stores (the moment
 // exchange is a lane shift).
 template <typename real, bool TAUF>
@@ -223,26 +224,38 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     const real kctv[4] = {-ksth, (real)SQH * (kcth - ksth), kcth, (real)SQH * (kcth + ksth)};
 
     // this lane's pairs 8 h .. 8 h + 7 (speeds 2 h + 1, 2 h + 2): directions
-    // dd of pair i in x[i], dd + 4 in x[i + 8]
-    real x[16], nbr[16], nbt[16], x0;
+    // dd of pair i in x[i], dd + 4 in x[i + 8].  Of each pair only one
+    // direction is kept (the one lane 0 or 63 takes from this side: dd + 4
+    // where `second`), so only its upwind neighbours are gathered, one value
+    // each: from the lower row if its C_r >= 0, from the left column if its
+    // C_theta >= 0 (direction dd + 4 has the opposite signs of dd).
+    real x[16], nbr[8], nbt[8], x0;
+    bool second[8];
     bload(x0, S.fin, o.x0, 0u);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const uint32_t po = pair_in_row(rb, 8 * h + i);
         const int dd = i & 3;
-        real lo0, lo1, hi0, hi1, l0, l1, r0, r1;
         bload2(x[i], x[i + 8], S.fin, o.orow + o.cc + po, 0u);
-        bload2(lo0, lo1, S.fin, o.olo + o.cc + po, 0u);
-        bload2(hi0, hi1, S.fin, o.ohi + o.cc + po, 0u);
-        bload2(l0, l1, S.fin, o.orow + o.cl + po, 0u);
-        bload2(r0, r1, S.fin, o.orow + o.cr + po, 0u);
-        const bool mr = crv[dd] >= (real)0, mt = ctv[dd] >= (real)0;
-        // direction dd takes the lower row if mr and the left column if mt,
-        // dd + 4 the other ones
-        nbr[i] = mr ? lo0 : hi0;
-        nbr[i + 8] = mr ? hi1 : lo1;
-        nbt[i] = mt ? l0 : r0;
-        nbt[i + 8] = mt ? r1 : l1;
+        second[i] = (kctv[dd] >= (real)0) == (side == 1);
+        const bool low = (crv[dd] >= (real)0) != second[i], left = (ctv[dd] >= (real)0) != second[i];
+        if constexpr (sizeof(real) == 4) {
+            const uint32_t mo = second[i] ? (uint32_t)sizeof(real) : 0u;  // the member within the pair
+            bload(nbr[i], S.fin, (low ? o.olo : o.ohi) + o.cc + po + mo, 0u);
+            bload(nbt[i], S.fin, o.orow + (left ? o.cl : o.cr) + po + mo, 0u);
+        } else {
+            // float64 (one wavefront per SIMD, nothing else to issue while
+            // the gathers are in flight): the four neighbour pairs from
+            // addresses known up front took less time than two from
+            // addresses chosen per lane
+            real lo0, lo1, hi0, hi1, l0, l1, r0, r1;
+            bload2(lo0, lo1, S.fin, o.olo + o.cc + po, 0u);
+            bload2(hi0, hi1, S.fin, o.ohi + o.cc + po, 0u);
+            bload2(l0, l1, S.fin, o.orow + o.cl + po, 0u);
+            bload2(r0, r1, S.fin, o.orow + o.cr + po, 0u);
+            nbr[i] = second[i] ? (low ? lo1 : hi1) : (low ? lo0 : hi0);
+            nbt[i] = second[i] ? (left ? l1 : r1) : (left ? l0 : r0);
+        }
     }
     double lc, lb, la, lL, lR;
     bload(lc, S.lin, o.lc, 0u);
@@ -275,25 +288,22 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
 
     const double ri = dp->r_min + ((double)r + 0.5) * dp->dr;
     const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
-    real g[16];
+    real g[8];
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
         const real v = kk == 0 ? va : vb;
         const real Fk = h == 0 ? C.F[1 + kk] : C.F[3 + kk];
         const real rF = C.rho * Fk;
-        const real Ak = C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T);
+        const real rA = rF * (C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T)), rB = rF * C.Bz;
 #pragma unroll
         for (int dd = 0; dd < 4; ++dd) {
             const int i = 4 * kk + dd;
-            const real z = v * C.EP.w(dd);
-            real pp, pm;
-            C.EP.eval(z, pp, pm);
-            const real bz = C.Bz * z;
+            // the same arithmetic as stage A of the strip owning the column
             const real acr = fabs(crv[dd]) * kr, act = fabs(ctv[dd]) * kt;
-            const real c0v = rF * pp * (Ak + bz) + C.omega * x[i];
-            const real c1v = rF * pm * (Ak - bz) + C.omega * x[i + 8];
-            g[i] = c0v - v * (acr * (x[i] - nbr[i]) + act * (x[i] - nbt[i]));
-            g[i + 8] = c1v - v * (acr * (x[i + 8] - nbr[i + 8]) + act * (x[i + 8] - nbt[i + 8]));
+            real E, O;
+            pair_coll(C.EP, v * C.EP.w(dd), rA, rB, E, O);
+            const real s = C.omega - v * (acr + act);
+            g[i] = dir_new(second[i] ? E - O : E + O, s, second[i] ? x[i + 8] : x[i], v, acr, act, nbr[i], nbt[i]);
         }
     }
     const double uxd = (double)C.ux, uyd = (double)C.uy;
@@ -305,11 +315,7 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
         C.reacted(dp, lc) - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
     if (e < count) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int dd = i & 3;
-            const bool first = (kctv[dd] >= (real)0) != (side == 1);  // keep direction dd, else dd + 4
-            ef[side][e][8 * h + i] = first ? g[i] : g[i + 8];
-        }
+        for (int i = 0; i < 8; ++i) ef[side][e][8 * h + i] = g[i];
         if (h == 0) el[side][e] = lnew;
     }
 }
@@ -332,6 +338,19 @@ __device__ __forceinline__ void fill_behind(real (*behind)[64], const real x[NQ]
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int dd = 0; dd < 4; ++dd) behind[4 * k + dd][lane] = mr[dd] ? x[1 + 8 * k + dd] : x[5 + 8 * k + dd];
+}
+
+// Exchanges two float32 rows of f in registers at the end of a pass.
+// Written as plain copies, the loop-carried exchange became three moves per
+// value (through a temporary, in three places of the loop); one v_swap_b32
+// per value does it (33 instructions instead of 99 per pass).  The s_nop
+// gives the two wait states a DPP read of a VGPR needs after a VALU write of
+// it, which the compiler does not insert after inline asm.
+__device__ __forceinline__ void swap_rows(float (&a)[NQ], float (&b)[NQ])
+{
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) asm("v_swap_b32 %0, %1" : "+v"(a[q]), "+v"(b[q]));
+    asm volatile("s_nop 1");
 }
 
 // Work of one wavefront of the two-step kernel: strip `strip`, rows [i0, i1)
@@ -457,11 +476,17 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
             stage_row<real, false, TAUF>(S, ir - step, gb, gc, nullptr, ga, nullptr, H, glp, glc, gln, mr, mt, acr, ctv,
                                          !down, cs.x, cs.y, unused, DB, diagB);
         }
+        if constexpr (sizeof(real) == 4) {
+            swap_rows(fc, fn);
+        } else {
+            // float64: one 64-bit move per copy (the same exchange moved into
+            // a function came out with 90 more AGPR moves per pass)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const real t = fc[q];
-            fc[q] = fn[q];
-            fn[q] = t;
+            for (int q = 0; q < NQ; ++q) {
+                const real t = fc[q];
+                fc[q] = fn[q];
+                fn[q] = t;
+            }
         }
         hc = hn;
         hn = hx;

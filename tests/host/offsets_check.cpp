@@ -120,13 +120,16 @@ void check_grid(const Grid &g)
                 for (int i = 0; i < 16; ++i) {
                     const uint32_t po = pair_in_row(b, i);
                     access(g, "edge pair", 0, 0, o.orow + o.cc + po, 2 * es, F, strip, r);
-                    access(g, "edge pair below", 0, 0, o.olo + o.cc + po, 2 * es, F, strip, r);
-                    access(g, "edge pair above", 0, 0, o.ohi + o.cc + po, 2 * es, F, strip, r);
-                    access(g, "edge pair left", 0, 0, o.orow + o.cl + po, 2 * es, F, strip, r);
-                    access(g, "edge pair right", 0, 0, o.orow + o.cr + po, 2 * es, F, strip, r);
+                    // one member (either) of the upwind neighbours' pairs
+                    for (uint32_t mo : {0u, es}) {
+                        access(g, "edge member below", 0, 0, o.olo + o.cc + po + mo, es, F, strip, r);
+                        access(g, "edge member above", 0, 0, o.ohi + o.cc + po + mo, es, F, strip, r);
+                        access(g, "edge member left", 0, 0, o.orow + o.cl + po + mo, es, F, strip, r);
+                        access(g, "edge member right", 0, 0, o.orow + o.cr + po + mo, es, F, strip, r);
+                    }
                     // the per-lane sums above must not wrap either
-                    const uint64_t far = (uint64_t)o.ohi + o.cc + po;
-                    access(g, "edge sum", far, (uint32_t)far, 0, 2 * es, F, strip, r);
+                    const uint64_t far = (uint64_t)o.ohi + o.cc + po + es;
+                    access(g, "edge sum", far, (uint32_t)far, 0, es, F, strip, r);
                 }
                 for (uint32_t lo : {o.lc, o.lb, o.la, o.lL, o.lR}) access(g, "edge lambda", 0, 0, lo, 8, L, strip, r);
                 access(g, "edge tau field", 0, 0, o.om, es, OM, strip, r);

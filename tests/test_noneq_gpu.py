@@ -114,10 +114,16 @@ def test_noneq_batch_member_and_async_match_solo():
     b.step(25)
     for i, w in enumerate(ws):
         solo = P.Solver(_params(w), P.make_ic(**w.ic_kw()))
-        for _ in range(25):  # one step per launch, as the packed members
-            solo.step(1)
+        for _ in range(5):  # as the pack's chunks: two pairs of steps, then one step
+            solo.step(5)
         D = solo.noneq()
-        assert np.array_equal(b.noneq(i), D)
+        # the pack's single steps run the one-step march inside the two-step
+        # kernel, the solo's a launch of the one-step kernel: equal to
+        # rounding (a member read from the other buffer, one step off,
+        # would differ by about 1e-5 of the scale)
+        err = _scaled_errors(b.noneq(i), D, solo.moments()[0])
+        print("member", i, "vs solo", f"{err.max():.1e}", flush=True)
+        assert err.max() <= 1e-13
         t = torch.empty((P.PDBM_NONEQ_N, w.nr, w.ntheta), dtype=torch.float64, device="cuda")
         solo.noneq_async(t)
         torch.cuda.synchronize()
