@@ -74,3 +74,28 @@ def test_rotated_sector_halos(nt, sector):
     s.step(w.nsteps)
     F, _ = s.moments(check=False)
     _check(F, w)
+
+
+@pytest.mark.parametrize("nt", [256, 512, 768])
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_strip_groups_of_whole_workgroups(nt, precision):
+    """Widths of whole workgroups of strips (multiples of 256: 4, 8 and 12
+    strips, so that the four wavefronts of a workgroup hold adjacent strips
+    of one row block, the last one's right neighbour being the first
+    strip).  Row counts leave blocks of one or a few rows; odd step counts
+    end with a one-step launch.  Float64 against the oracle at the parity
+    bound, float32 at its own."""
+    tol = TOL64 if precision == P.PDBM_FP64 else 1e-4
+    for nr, nsteps in ((1, 12), (5, 13), (33, 12), (70, 9)):
+        w = replace(_case(nr, nt), nsteps=nsteps)
+        s = P.Solver(P.make_params(**w.params_kw(), precision=precision), P.make_ic(**w.ic_kw()))
+        s.step(w.nsteps)
+        F, _ = s.moments(check=False)
+        o = O.Solver(O.make_params(**w.params_kw()))
+        o.init_ic(**w.ic_kw())
+        o.step(w.nsteps)
+        R = o.fields()
+        sc = _scales(R)
+        err = np.array([np.abs(F[k] - R[k]).max() / sc[k] for k in range(6)])
+        print(f"nt={nt} nr={nr} steps={nsteps} precision={precision}: max err {err.max():.2e}", flush=True)
+        assert np.isfinite(err).all() and err.max() < tol, (nr, nt, err)
