@@ -193,6 +193,40 @@ def test_server_failure_is_isolated():
     srv.close()
 
 
+def test_stream_request_that_turns_nonphysical_is_reported_failed():
+    """Request 138 of the 1000-request serving stream (430 x 1952, m = 2,
+    n = 3) is one the model cannot carry: the oracle's own run has no bad
+    cell at step 350 and non-finite and non-physical cells at step 400
+    (tests/golden/unstable_request.json, written from the oracle alone).
+    The float64 path reaches the same verdict at both steps, and the server,
+    serving it in float32 beside a stable request of the stream, reports it
+    failed and the other done."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "unstable_request.json")))
+    stream = W.serving_stream(count=1000, rate=30.0)
+    w = stream[g["index"]][1]
+    assert (w.nr, w.ntheta, w.nsteps, w.m, w.n) == (g["nr"], g["ntheta"], g["nsteps"], g["m"], g["n"])
+    s = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64, diag_every=50), P.make_ic(**w.ic_kw()))
+    s.step(401)  # the record of step s holds the state the step starts from
+    hist = {r["step"]: r for r in s.diag_history()}
+    s.close()
+    for step in (350, 400):
+        oracle_bad = sum(g["oracle_bad_cells"][str(step)].values()) > 0
+        gpu_bad = hist[step]["n_nonfinite"] + hist[step]["n_nonphys"] > 0
+        print("step", step, "oracle bad", oracle_bad, "float64 path", hist[step], flush=True)
+        assert gpu_bad == oracle_bad, step
+    ok = stream[1][1]
+    srv = P.Server(hbm_cap_bytes=50 * 10**9, max_slots=8, chunk_steps=24)
+    bid = srv.submit(_params(w, P.PDBM_FP32), P.make_ic(**w.ic_kw()), w.nsteps)
+    oid = srv.submit(_params(ok, P.PDBM_FP32), P.make_ic(**ok.ic_kw()), ok.nsteps)
+    assert srv.wait(120.0)
+    state, _, d = srv.poll(bid)
+    assert state == P.PDBM_FAILED and d["n_nonfinite"] + d["n_nonphys"] > 0
+    assert srv.poll(oid)[0] == P.PDBM_DONE
+    srv.close()
+
+
 def test_server_shutdown_with_pending_work():
     w = _small_sweep(1, seed=7)[0]
     srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=1, chunk_steps=5)
