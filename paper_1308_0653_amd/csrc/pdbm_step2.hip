@@ -178,36 +178,52 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
     if (diag) D.add(store, (double)C.rho, uxd, uyd, C.Td, (double)C.e, lc, ri * dp->dr * dp->dth, dp->Q);
 }
 
-// The value the other lane of a lane pair (lanes 2m, 2m + 1) holds.
-__device__ __forceinline__ float pair_swap(float v)
+// The value lane l ^ x holds, x = 1 or 2 (a permutation within each group of
+// four lanes).
+template <int X>
+__device__ __forceinline__ float lane_xor(float v)
 {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xf, 0xf, false));
+    constexpr int ctl = X == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] or [2,3,0,1]
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctl, 0xf, 0xf, false));
 }
-__device__ __forceinline__ double pair_swap(double v)
+template <int X>
+__device__ __forceinline__ double lane_xor(double v)
 {
-    return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xf, 0xf, false),
-                            __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xf, 0xf, false));
+    constexpr int ctl = X == 1 ? 0xB1 : 0x4E;
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), ctl, 0xf, 0xf, false),
+                            __builtin_amdgcn_mov_dpp(__double2loint(v), ctl, 0xf, 0xf, false));
+}
+// The sum of v over the LPC lanes of a cell (2 or 4 adjacent lanes).
+template <int LPC, typename T>
+__device__ __forceinline__ T cell_sum(T v)
+{
+    v += lane_xor<1>(v);
+    if constexpr (LPC == 4) v += lane_xor<2>(v);
+    return v;
 }
 
 // The intermediate state at the columns bordering strip `strip`, c0 - 1
 // (left) and c0 + 64 (right) as periodic images, for the rows [i0, i1) of the
-// block.  Two lanes take one cell: lane 32 side + 2 e + h takes row i0 + e of
-// its side, h = 0 the speeds 1 and 2 (and the rest particle), h = 1 the
-// speeds 3 and 4.  Of each opposite pair of directions only the one that
-// lane 0 (left side) or lane 63 (right side) takes from there is kept.  Each
-// lane gathers its pairs of the cell (one access per pair) and, for the kept
-// direction of each, its two upwind neighbours (radial ghost rules of
-// Sec. II.D included); the two lanes add up their partial moments, and each
-// updates its kept directions as stage A of the strip owning the column
-// does.  The first lane of the two keeps lambda.
-// Every lane runs every instruction up to the final stores (the moment
-// exchange is a lane shift).
-template <typename real, bool TAUF>
+// block.  LPC lanes (2, or 4 for blocks of at most 8 rows) take one cell:
+// lane 32 side + LPC e + h takes row i0 + e of its side and the speeds
+// 4 h / LPC + 1 .. 4 (h + 1) / LPC (h = 0 also the rest particle).  Of each
+// opposite pair of directions only the one that lane 0 (left side) or lane
+// 63 (right side) takes from there is kept.  Each lane gathers its pairs of
+// the cell (one access per pair) and, for the kept direction of each, its
+// two upwind neighbours (radial ghost rules of Sec. II.D included); the
+// lanes of a cell add up their partial moments, and each updates its kept
+// directions as stage A of the strip owning the column does.  The first
+// lane of a cell keeps lambda.  Every lane runs every instruction up to the
+// final stores (the moment exchange is a lane permutation).
+template <typename real, bool TAUF, int LPC>
 __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int strip, int i0, int i1,
                                            real (*ef)[FUSE_ROWS][16], double (*el)[FUSE_ROWS])
 {
+    static_assert(LPC == 2 || LPC == 4, "two or four lanes per cell");
+    constexpr int NP = 16 / LPC;  // pairs per lane
+    constexpr int NS = 4 / LPC;   // speeds per lane
     const DescPtr dp = S.dp;
-    const int lane = S.lane, side = lane >> 5, e = (lane >> 1) & 15, h = lane & 1;
+    const int lane = S.lane, side = lane >> 5, e = (lane & 31) / LPC, h = lane & (LPC - 1);
     const int count = i1 - i0;
     const int nr = dp->nr, nt = dp->nt;
     const int r = i0 + min(e, count - 1);  // lanes past the block repeat its last row
@@ -223,20 +239,20 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     const real kcth = (real)ck.x, ksth = (real)ck.y;
     const real kctv[4] = {-ksth, (real)SQH * (kcth - ksth), kcth, (real)SQH * (kcth + ksth)};
 
-    // this lane's pairs 8 h .. 8 h + 7 (speeds 2 h + 1, 2 h + 2): directions
-    // dd of pair i in x[i], dd + 4 in x[i + 8].  Of each pair only one
-    // direction is kept (the one lane 0 or 63 takes from this side: dd + 4
-    // where `second`), so only its upwind neighbours are gathered, one value
-    // each: from the lower row if its C_r >= 0, from the left column if its
-    // C_theta >= 0 (direction dd + 4 has the opposite signs of dd).
-    real x[16], nbr[8], nbt[8], x0;
-    bool second[8];
+    // this lane's pairs NP h .. NP h + NP - 1: directions dd of pair i in
+    // x[i], dd + 4 in x[i + NP].  Of each pair only one direction is kept
+    // (the one lane 0 or 63 takes from this side: dd + 4 where `second`), so
+    // only its upwind neighbours are gathered, one value each: from the lower
+    // row if its C_r >= 0, from the left column if its C_theta >= 0
+    // (direction dd + 4 has the opposite signs of dd).
+    real x[2 * NP], nbr[NP], nbt[NP], x0;
+    bool second[NP];
     bload(x0, S.fin, o.x0, 0u);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const uint32_t po = pair_in_row(rb, 8 * h + i);
+    for (int i = 0; i < NP; ++i) {
+        const uint32_t po = pair_in_row(rb, NP * h + i);
         const int dd = i & 3;
-        bload2(x[i], x[i + 8], S.fin, o.orow + o.cc + po, 0u);
+        bload2(x[i], x[i + NP], S.fin, o.orow + o.cc + po, 0u);
         second[i] = (kctv[dd] >= (real)0) == (side == 1);
         const bool low = (crv[dd] >= (real)0) != second[i], left = (ctv[dd] >= (real)0) != second[i];
         if constexpr (sizeof(real) == 4) {
@@ -264,35 +280,46 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     bload(lL, S.lin, o.lL, 0u);
     bload(lR, S.lin, o.lR, 0u);
 
-    // moments: this lane's two rings (summed as raw_moments does), then the
-    // other lane's added
-    const real va = h == 0 ? (real)speed(1) : (real)speed(3), vb = h == 0 ? (real)speed(2) : (real)speed(4);
+    // moments: this lane's rings (summed as raw_moments does), then the
+    // other lanes' added
+    real vk[NS];  // this lane's speeds
+#pragma unroll
+    for (int kk = 0; kk < NS; ++kk) {
+        if constexpr (LPC == 2)
+            vk[kk] = h == 0 ? (real)speed(1 + kk) : (real)speed(3 + kk);
+        else
+            vk[kk] = h == 0 ? (real)speed(1) : h == 1 ? (real)speed(2) : h == 2 ? (real)speed(3) : (real)speed(4);
+    }
     real rho = h == 0 ? x0 : (real)0, jx = 0, jy = 0, en = 0;
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-        const real *g = x + 4 * kk;  // directions 0..3 at g[0..3], 4..7 at g[8..11]
-        const real v = kk == 0 ? va : vb;
-        const real ring = ((g[0] + g[8]) + (g[2] + g[10])) + ((g[1] + g[9]) + (g[3] + g[11]));
-        const real a15 = g[1] - g[9], a37 = g[3] - g[11];
-        const real X = (g[0] - g[8]) + (real)SQH * (a15 - a37);
-        const real Y = (g[2] - g[10]) + (real)SQH * (a15 + a37);
+    for (int kk = 0; kk < NS; ++kk) {
+        const real *g = x + 4 * kk;  // directions 0..3 at g[0..3], 4..7 at g[NP..NP + 3]
+        const real v = vk[kk];
+        const real ring = ((g[0] + g[NP]) + (g[2] + g[NP + 2])) + ((g[1] + g[NP + 1]) + (g[3] + g[NP + 3]));
+        const real a15 = g[1] - g[NP + 1], a37 = g[3] - g[NP + 3];
+        const real X = (g[0] - g[NP]) + (real)SQH * (a15 - a37);
+        const real Y = (g[2] - g[NP + 2]) + (real)SQH * (a15 + a37);
         rho += ring;
         jx += v * X;
         jy += v * Y;
         en += (real)0.5 * v * v * ring;
     }
     Cell<real> C;
-    C.rho = rho + pair_swap(rho);
-    C.e = en + pair_swap(en);
-    C.init_moments(dp, jx + pair_swap(jx), jy + pair_swap(jy), lc, omega_at<real, TAUF>(dp, o.om, 0u));
+    C.rho = cell_sum<LPC>(rho);
+    C.e = cell_sum<LPC>(en);
+    C.init_moments(dp, cell_sum<LPC>(jx), cell_sum<LPC>(jy), lc, omega_at<real, TAUF>(dp, o.om, 0u));
 
     const double ri = dp->r_min + ((double)r + 0.5) * dp->dr;
     const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
-    real g[8];
+    real g[NP];
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-        const real v = kk == 0 ? va : vb;
-        const real Fk = h == 0 ? C.F[1 + kk] : C.F[3 + kk];
+    for (int kk = 0; kk < NS; ++kk) {
+        const real v = vk[kk];
+        real Fk;
+        if constexpr (LPC == 2)
+            Fk = h == 0 ? C.F[1 + kk] : C.F[3 + kk];
+        else
+            Fk = h == 0 ? C.F[1] : h == 1 ? C.F[2] : h == 2 ? C.F[3] : C.F[4];
         const real rF = C.rho * Fk;
         const real rA = rF * (C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T)), rB = rF * C.Bz;
 #pragma unroll
@@ -303,7 +330,7 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
             real E, O;
             pair_coll(C.EP, v * C.EP.w(dd), rA, rB, E, O);
             const real s = C.omega - v * (acr + act);
-            g[i] = dir_new(second[i] ? E - O : E + O, s, second[i] ? x[i + 8] : x[i], v, acr, act, nbr[i], nbt[i]);
+            g[i] = dir_new(second[i] ? E - O : E + O, s, second[i] ? x[i + NP] : x[i], v, acr, act, nbr[i], nbt[i]);
         }
     }
     const double uxd = (double)C.ux, uyd = (double)C.uy;
@@ -315,7 +342,7 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
         C.reacted(dp, lc) - fabs(urp) * dp->dt_dr * (lc - lr) - fabs(utp) * (dp->dt_dth / ri) * (lc - lt);
     if (e < count) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) ef[side][e][8 * h + i] = g[i];
+        for (int i = 0; i < NP; ++i) ef[side][e][NP * h + i] = g[i];
         if (h == 0) el[side][e] = lnew;
     }
 }
@@ -423,7 +450,14 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
     // gathers, to wait for memory once, took more time in both precisions
     // (97.7 against 95.1 us per float32 launch), the rows held through the
     // edge cells
-    edge_cells<real, TAUF>(S, strip, i0, i1, ef, el);
+    // float32 blocks of up to 8 rows: four lanes per edge cell, so that the
+    // 2 x 8 cells keep all 64 lanes busy (93.9 against 95.3 us per launch);
+    // float64 keeps two (its 16-row blocks fill the lanes with two; with
+    // both forms compiled into its kernel it ran 2 us per launch slower)
+    if (sizeof(real) == 4 && i1 - i0 <= 8)
+        edge_cells<real, TAUF, 4>(S, strip, i0, i1, ef, el);
+    else
+        edge_cells<real, TAUF, 2>(S, strip, i0, i1, ef, el);
     load_first_rows();
     fill_behind(fb, t, mr, lane);
     wave_lds_sync();
