@@ -184,11 +184,31 @@ __device__ __forceinline__ void equilibrium(const double *A, real rho, real ux, 
     }
 }
 
+// Sum of x over the wavefront (every lane must be active), in a fixed order:
+// pairs, quads, half rows and rows of 16 lanes by DPP (after which every
+// lane of a row holds the row's sum), then rows 1 and 3 add rows 0 and 2 by
+// broadcast of lanes 15 and 47, and rows 2 and 3 the first half by
+// broadcast of lane 31.  Lane 63 ends with the total, which is returned to
+// every lane.  The moves stay in the VALU: the LDS permutes of a butterfly
+// cost six dependent LDS round trips per value at the end of each
+// wavefront's work.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double x)
+{
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, false);
+    return x + __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double wave_sum(double x)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x = dpp_add<0xB1, 0xf>(x);   // quad_perm [1, 0, 3, 2]
+    x = dpp_add<0x4E, 0xf>(x);   // quad_perm [2, 3, 0, 1]
+    x = dpp_add<0x141, 0xf>(x);  // row_half_mirror
+    x = dpp_add<0x140, 0xf>(x);  // row_mirror
+    x = dpp_add<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x = dpp_add<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 63),
+                            __builtin_amdgcn_readlane(__double2loint(x), 63));
 }
 
 // Sums v[0..4] over the workgroup; the result is valid in thread 0.

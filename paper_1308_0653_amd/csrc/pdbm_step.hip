@@ -185,11 +185,12 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
     if (diag) {
         const int64_t slot = (step / dp->diag_every) % PART_RING;
         double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
+        double v[5];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            const double v = wave_sum(red[i]);
-            if ((threadIdx.x & 63) == 0) part[i] = v;
-        }
+        for (int i = 0; i < 5; ++i) v[i] = wave_sum(red[i]);
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int i = 0; i < 5; ++i) part[i] = v[i];
     }
 }
 

@@ -598,11 +598,12 @@ __global__ __launch_bounds__(BLOCK, Step2Occ<real>::waves) void k_step2(const So
         if (diag) {
             const int64_t slot = (step / dp->diag_every) % PART_RING;
             double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
+            double v[5];
 #pragma unroll
-            for (int i = 0; i < 5; ++i) {
-                const double v = wave_sum(red[i]);
-                if ((threadIdx.x & 63) == 0) part[i] = v;
-            }
+            for (int i = 0; i < 5; ++i) v[i] = wave_sum(red[i]);
+            if ((threadIdx.x & 63) == 0)
+#pragma unroll
+                for (int i = 0; i < 5; ++i) part[i] = v[i];
         }
         return;
     }
@@ -610,15 +611,22 @@ __global__ __launch_bounds__(BLOCK, Step2Occ<real>::waves) void k_step2(const So
     LaneDiag DA, DB;
     march2<real, TAUF>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], DA,
                        DB, diagA, diagB);
+    // both steps' totals first (independent DPP chains the compiler can
+    // interleave), then one lane stores them
+    double v[2][5];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        if (!(s == 0 ? diagA : diagB)) continue;
-        const int64_t slot = ((step + s) / dp->diag_every) % PART_RING;
-        double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
+    for (int i = 0; i < 5; ++i) {
+        v[0][i] = diagA ? DA.total(i) : 0.0;
+        v[1][i] = diagB ? DB.total(i) : 0.0;
+    }
+    if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            const double v = s == 0 ? DA.total(i) : DB.total(i);
-            if ((threadIdx.x & 63) == 0) part[i] = v;
+        for (int s = 0; s < 2; ++s) {
+            if (!(s == 0 ? diagA : diagB)) continue;
+            const int64_t slot = ((step + s) / dp->diag_every) % PART_RING;
+            double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) part[i] = v[s][i];
         }
     }
 }
