@@ -48,14 +48,23 @@ __device__ __forceinline__ double ipow(double x, int e)
     return y;
 }
 
-// F_k(T), k = 0..4, from the moment-inversion matrix (Horner in T, float64).
+// F_k(T), k = 0..4, from the moment-inversion matrix, in float64: the
+// powers T .. T^4 once, then each F_k as a sum of A_kn T^n.  (In Horner form
+// each step adds a coefficient, which sits in a scalar register; the
+// compiler's multiply-add takes its addend in the destination register, so
+// every coefficient first took two moves into vector registers.  Here the
+// coefficients are multiplicands, read from the scalar registers directly.)
 template <typename real>
 __device__ __forceinline__ void weights(const double *A, double T, real F[5])
 {
+    const double T2 = T * T, T3 = T2 * T, T4 = T2 * T2;
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const double v = T * (A[4 * k] + T * (A[4 * k + 1] + T * (A[4 * k + 2] + T * A[4 * k + 3])));
+        double v = A[4 * k] * T;
+        v = fma(A[4 * k + 1], T2, v);
+        v = fma(A[4 * k + 2], T3, v);
+        v = fma(A[4 * k + 3], T4, v);
         F[k + 1] = (real)v;
         s += v;
     }
