@@ -486,8 +486,18 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
     if (!h || nsteps < 0) return fail(PDBM_EINVAL, "bad solver or step count");
     Solve &s = h->s;
     const bool pairs = s.fusable();
+    const bool column = s.p.ntheta == 1;
+    const int most = column ? COL_K : 2;  // steps of one launch, at most
     for (int64_t i = 0; i < nsteps;) {
-        if (pairs && nsteps - i >= 2) {
+        if (column) {
+            // a single column: up to COL_K steps per launch; the state moves
+            // to the other buffer, which toggles the parity unless nk is odd
+            const int nk = (int)std::min<int64_t>(COL_K, nsteps - i);
+            HIPCHK(launch_column(s.dd, s.waves(), s.step, s.flip, nk, s.fp32, s.tauf(), h->st));
+            s.step += nk;
+            s.flip ^= (nk + 1) & 1;
+            i += nk;
+        } else if (pairs && nsteps - i >= 2) {
             HIPCHK(launch_step2(s.dd, nullptr, s.waves(), nullptr, s.step, nullptr, s.flip, false, s.fp32, s.tauf(),
                                 h->st));
             s.step += 2;
@@ -500,8 +510,8 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
             i += 1;
         }
         // the partial-sum ring holds PART_RING records: add them up before
-        // the next launch (at most two steps) could overwrite one
-        if (s.step - s.red_to > PART_RING - 2) {
+        // the next launch (at most `most` steps) could overwrite one
+        if (s.step - s.red_to > PART_RING - most) {
             int rc = s.reduce_records(h->st);
             if (rc) return rc;
         }

@@ -17,6 +17,8 @@ constexpr int NXCD = 8;         // accelerator complex dies of an MI355X
 constexpr int NONEQ = PDBM_NONEQ_N;  // components of the non-equilibrium measures
 constexpr int STRIP = 64;       // theta columns stored per wavefront, one per lane
 constexpr int FUSE_ROWS = 16;   // most rows per wavefront of the two-step kernel (its edge cells sit in LDS)
+constexpr int COL_K = 8;                  // steps per launch of the single-column kernel, at most
+constexpr int COL_W = STRIP - 2 * COL_K;  // rows a wavefront owns in a single-column solve (48)
 
 // Layout of f within one r row (33 * pitch elements): the rest particle's
 // plane [pitch], then the 16 pairs of opposite directions of each speed, pair
@@ -87,6 +89,11 @@ struct DiagCtl {
 // left.
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
                        const int *flips, int flip, bool fp32, bool rot, bool tauf, hipStream_t st);
+// Up to COL_K steps (nk) of a single-column single solve (ntheta = 1) in one
+// launch of k_column; the state of step0 is in buffer (step0 + flip) & 1 and
+// the new one goes to the other buffer.
+hipError_t launch_column(const SolveDesc *desc, int nwaves, int64_t step0, int flip, int nk, bool fp32, bool tauf,
+                         hipStream_t st);
 // Steps s and s + 1 of every solve of the launch in one pass (tiles, bases,
 // step_off, flips and flip as launch_step): reads buffer (s + flip_i) & 1 and
 // writes the other one, so the caller toggles flip_i.  A solve with one step

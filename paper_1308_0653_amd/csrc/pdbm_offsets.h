@@ -138,10 +138,11 @@ __host__ __device__ inline EdgeOffsets edge_offsets(int nr, int nt, int esz, con
 // Offset of pair i (0..15) within a row of f (column 0).
 __host__ __device__ inline uint32_t pair_in_row(const RowBytes &b, int i) { return b.rest + (uint32_t)i * b.pair; }
 
-// The single-column kernel (radial_block in pdbm_step.hip): lane l of block
-// blk owns row re = min(64 blk + l, nr - 1) of column 0 and gathers the row
-// below the block (rlo, directions turned by `tlo` at the disc centre) and
-// the row above it (rhi).
+// The one-step single-column kernel (radial_block in pdbm_step.hip): lane l
+// of block blk holds row re = min(COL_W blk + l, nr - 1) of column 0 (it
+// owns the rows of lanes below COL_W) and gathers the row below the block
+// (rlo, directions turned by `tlo` at the disc centre) and the row 64 above
+// its first (rhi).
 struct RadialOffsets {
     int re, rlo, rhi;
     uint32_t vo, vol;     // the lane's row: f and lambda
@@ -152,7 +153,7 @@ __host__ __device__ inline RadialOffsets radial_offsets(int nr, int64_t pitch, b
                                                         int blk, int lane)
 {
     RadialOffsets o;
-    const int r0 = blk * 64;
+    const int r0 = blk * COL_W;
     const int row = r0 + lane;
     o.re = row < nr - 1 ? row : nr - 1;  // lanes past the last row hold its zero-gradient image
     o.rlo = r0 == 0 ? 0 : r0 - 1;
@@ -166,6 +167,29 @@ __host__ __device__ inline RadialOffsets radial_offsets(int nr, int64_t pitch, b
     o.vh2 = lane < 2 ? (uint32_t)o.rhi * b.row + (uint32_t)elem_of(31 + lane, 0, pitch) * es
                      : (uint32_t)o.rlo * b.row;
     o.vhl = lane == 1 ? (uint32_t)o.rhi * b.lrow : (uint32_t)o.rlo * b.lrow;
+    o.om = (uint32_t)o.re * b.rest;
+    return o;
+}
+
+// The multi-step single-column kernel (k_column in pdbm_step.hip): lane l
+// of wavefront t holds row r0 - COL_K + l, r0 = COL_W t, whose data it
+// loads from row re (the row clamped to the grid: rows outside it start as
+// their radial ghosts), and owns it if it is one of rows r0 .. r0 + COL_W - 1
+// of the grid (then it stores the new state there).
+struct ColumnOffsets {
+    int row, re;
+    bool own;
+    uint32_t vo, vol, om;  // f (rest plane of the row; pairs follow), lambda, the per-cell tau field
+};
+__host__ __device__ inline ColumnOffsets column_offsets(int nr, const RowBytes &b, int t, int lane)
+{
+    ColumnOffsets o;
+    const int r0 = t * COL_W;
+    o.row = r0 - COL_K + lane;
+    o.re = o.row < 0 ? 0 : o.row > nr - 1 ? nr - 1 : o.row;
+    o.own = lane >= COL_K && lane < COL_K + COL_W && o.row < nr;
+    o.vo = (uint32_t)o.re * b.row;
+    o.vol = (uint32_t)o.re * b.lrow;
     o.om = (uint32_t)o.re * b.rest;
     return o;
 }

@@ -8,11 +8,13 @@
 namespace pdbm {
 namespace {
 
-// One step of 64 consecutive rows of a solve with a single theta column
-// (ntheta = 1, the quasi-one-dimensional runs of Sec. III): lane l owns row
-// 64 blk + l.  Radial neighbours come from the adjacent lanes (DPP shifts)
-// and, for lanes 0 and 63, from gathers of the rows below and above the
-// block, which apply the radial ghost rules of Sec. II.D.  The azimuthal
+// One step of the rows of a solve with a single theta column (ntheta = 1,
+// the quasi-one-dimensional runs of Sec. III) in packed launches: lane l
+// holds row COL_W blk + l and owns it for l < COL_W (the rows a wavefront
+// owns are those of k_column, so that the two keep the same per-wavefront
+// drift partial sums).  Radial neighbours come from the adjacent lanes (DPP
+// shifts) and, for lanes 0 and 63, from gathers of the rows below and above
+// the block, which apply the radial ghost rules of Sec. II.D.  The azimuthal
 // neighbours of a cell are the cell itself with directions turned by the
 // sector (periodic halo, f_{k,i}(j-1) = f_{k,(i+s)%8}(j) and f_{k,i}(j+1) =
 // f_{k,(i-s)%8}(j)); they are read back from the wavefront's LDS slot.
@@ -23,7 +25,7 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
 {
     const int lane = threadIdx.x & 63;
     const int nr = dp->nr, sec = dp->sector;
-    const bool store = blk * 64 + lane < nr;
+    const bool store = lane < COL_W && blk * COL_W + lane < nr;
     const __amdgpu_buffer_rsrc_t fin = rsrc_of(bufs.f_in), fout = rsrc_of(bufs.f_out);
     const __amdgpu_buffer_rsrc_t lin = rsrc_of(bufs.lam_in), lout = rsrc_of(bufs.lam_out);
     const RowBytes b = row_bytes_of(dp->rstride, dp->pitch, (int)sizeof(real));
@@ -128,6 +130,167 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
     if (store) bstore(lnew, lout, vol, 0u);
 
     if (diag && store) diag_cell(red, (double)rho, uxd, uyd, Td, (double)e, lc, ri * dp->dr * dp->dth, dp->Q);
+}
+
+// Up to COL_K steps of a single-column solve in one launch (the
+// quasi-one-dimensional runs of Sec. III, single solves): wavefront t holds
+// rows r0 - COL_K .. r0 + 63 - COL_K, r0 = COL_W t, one per lane, and owns
+// rows r0 .. r0 + COL_W - 1 (column_offsets).  Each step updates every lane
+// from the lanes beside it (DPP shifts; lanes 0 and 63 read nothing from
+// outside and go wrong), so a wrong value moves in by one lane per step:
+// after k steps lanes k .. 63 - k still hold the true state, the owned lanes
+// after all COL_K.  Rows outside the grid hold the radial ghosts of
+// Sec. II.D: they are loaded from the boundary row and set from it again
+// before every step (a zero-gradient copy; at the disc centre row 0 with
+// directions turned by 4, lambda copied).  The azimuthal neighbours are the
+// cell itself with directions turned by the sector, as in radial_block, and
+// the arithmetic per cell is the same.  Drift partial sums of each recorded
+// step come from the owned lanes' state at the start of that step.
+template <typename real, bool TAUF>
+__global__ __launch_bounds__(BLOCK, 1) void k_column(const SolveDesc *desc, int64_t step0, int flip, int nk)
+{
+    const DescPtr dp = (DescPtr)desc;
+    const int nb = gridDim.x;
+    const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, nb) * (BLOCK / 64) + (threadIdx.x >> 6));
+    if (t >= dp->nwaves) return;
+    __shared__ real slots[BLOCK / 64][NQ][64];
+    real(*slot)[64] = slots[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int nr = dp->nr, sec = dp->sector;
+    const int cur = (int)((step0 + flip) & 1);
+    const __amdgpu_buffer_rsrc_t fin = rsrc_of(dp->f[cur]), fout = rsrc_of(dp->f[cur ^ 1]);
+    const __amdgpu_buffer_rsrc_t lin = rsrc_of(dp->lam[cur]), lout = rsrc_of(dp->lam[cur ^ 1]);
+    const RowBytes b = row_bytes_of(dp->rstride, dp->pitch, (int)sizeof(real));
+    const ColumnOffsets o = column_offsets(nr, b, t, lane);
+    const bool below = o.row < 0, above = o.row >= nr;
+    const bool disc = dp->disc;
+    // lanes of the first and the last row of the grid, where the wavefront holds them
+    const int r_first = t * COL_W - COL_K;
+    const int l_first = -r_first, l_last = nr - 1 - r_first;
+    const bool has_below = r_first < 0, has_above = r_first + 63 >= nr;
+
+    // the state at step0 (rows below the grid: row 0, its pairs' members
+    // exchanged at the disc centre, which turns each direction by 4)
+    real fc[NQ];
+    double lc;
+    bload(fc[0], fin, o.vo, 0u);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        real a, bb;
+        bload2(a, bb, fin, o.vo, b.rest + (uint32_t)c * b.pair);
+        const int q = 1 + 8 * (c >> 2) + (c & 3);
+        const bool turn = below && disc;
+        fc[q] = turn ? bb : a;
+        fc[q + 4] = turn ? a : bb;
+    }
+    bload(lc, lin, o.vol, 0u);
+    const real om = omega_at<real, TAUF>(dp, o.om, 0u);
+
+    // polar components of directions dd = 0..3 at theta_0 (dd+4 is the negative)
+    const double2 cs = dp->cs[0];
+    const real cth = (real)cs.x, sth = (real)cs.y;
+    const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
+    const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
+    const double ri = dp->r_min + ((double)o.re + 0.5) * dp->dr;
+    const real kr = (real)dp->dt_dr, kt = (real)(dp->dt_dth / ri);
+    real acr[4], act[4];
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        acr[dd] = fabs(crv[dd]) * kr;
+        act[dd] = fabs(ctv[dd]) * kt;
+    }
+    const double w_area = ri * dp->dr * dp->dth;
+
+    for (int j = 0; j < nk; ++j) {
+        const int64_t step = step0 + j;
+        if (j > 0 && has_below) {
+            // rows below the grid: the ghost of row 0 (lane l_first)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int qs = (q == 0 || !disc) ? q : 1 + 8 * ((q - 1) >> 3) + ((((q - 1) & 7) + 4) & 7);
+                const real g = lane_value(fc[qs], l_first);
+                fc[q] = below ? g : fc[q];
+            }
+            const double g = lane_value(lc, l_first);
+            lc = below ? g : lc;
+        }
+        if (j > 0 && has_above) {
+            // rows above the grid: the copy of row nr - 1 (lane l_last)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const real g = lane_value(fc[q], l_last);
+                fc[q] = above ? g : fc[q];
+            }
+            const double g = lane_value(lc, l_last);
+            lc = above ? g : lc;
+        }
+
+        const Cell<real> C(dp, fc, lc, om);
+        if (records(dp, step)) {
+            double red[5] = {0, 0, 0, 0, 0};
+            if (o.own)
+                diag_cell(red, (double)C.rho, (double)C.ux, (double)C.uy, C.Td, (double)C.e, lc, w_area, dp->Q);
+            double v[5];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) v[i] = wave_sum(red[i]);
+            double *part = dp->wpart + (((size_t)((step / dp->diag_every) % PART_RING)) * dp->nwaves + t) * 5;
+            if (lane == 0)
+#pragma unroll
+                for (int i = 0; i < 5; ++i) part[i] = v[i];
+        }
+
+        // the cell's distributions, for its rotated azimuthal neighbours
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) slot[q][lane] = fc[q];
+        real fn[NQ];
+        fn[0] = C.rest(fc[0]);
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            const real v = (real)speed(k);
+            const real rF = C.rho * C.F[k];
+            const real rA = rF * (C.keep + C.beta * (v * v + C.u2 - (real)2 * C.T)), rB = rF * C.Bz;
+            const int base = 1 + 8 * (k - 1);
+#pragma unroll
+            for (int dd = 0; dd < 4; ++dd) {
+                real E, O;
+                pair_coll(C.EP, v * C.EP.w(dd), rA, rB, E, O);
+                const real s = C.omega - v * (acr[dd] + act[dd]);
+#pragma unroll
+                for (int sgn = 0; sgn < 2; ++sgn) {
+                    const int q = base + dd + 4 * sgn;
+                    const real x = fc[q];
+                    // radial upwind (C_r >= 0 takes the row below, lane - 1)
+                    const real lower = from_left(x), upper = from_right(x);
+                    const bool lo = sgn == 0 ? crv[dd] >= (real)0 : crv[dd] < (real)0;
+                    const real nbr = lo ? lower : upper;
+                    // azimuthal upwind: this cell, direction turned by +s or -s
+                    const bool left = sgn == 0 ? ctv[dd] >= (real)0 : ctv[dd] < (real)0;
+                    const int dir = dd + 4 * sgn;
+                    const real nbt = slot[base + ((dir + (left ? sec : 8 - sec)) & 7)][lane];
+                    fn[q] = dir_new(sgn == 0 ? E + O : E - O, s, x, v, acr[dd], act[dd], nbr, nbt);
+                }
+            }
+        }
+        // lambda: closed-form Cochran step, then upwind by own-cell u_r
+        const double uxd = (double)C.ux, uyd = (double)C.uy;
+        const double urp = uxd * cs.x + uyd * cs.y;
+        const double lreac = C.reacted(dp, lc);
+        const double llow = from_left(lc), lup = from_right(lc);
+        const double lr = urp >= 0.0 ? llow : lup;
+        lc = lreac - fabs(urp) * dp->dt_dr * (lc - lr);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) fc[q] = fn[q];
+    }
+
+    if (o.own) {
+        bstore(fc[0], fout, o.vo, 0u);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const int q = 1 + 8 * (c >> 2) + (c & 3);
+            bstore2(fc[q], fc[q + 4], fout, o.vo, b.rest + (uint32_t)c * b.pair);
+        }
+        bstore(lc, lout, o.vol, 0u);
+    }
 }
 
 // Occupancy: float32 rows fit two wavefronts per SIMD; float64 rows take
@@ -244,7 +407,7 @@ __global__ __launch_bounds__(64) void k_records(const SolveDesc *descs, const in
 
 int solve_waves(int nr, int nt, int rows)
 {
-    if (nt == 1) return (nr + STRIP - 1) / STRIP;  // lanes along r: 64 rows per wavefront
+    if (nt == 1) return (nr + COL_W - 1) / COL_W;  // lanes along r: COL_W rows per wavefront
     return (int)((int64_t)((nr + rows - 1) / rows) * ((nt + STRIP - 1) / STRIP));
 }
 
@@ -270,6 +433,25 @@ hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, c
         {{launch_k_step<float, false, false>, launch_k_step<float, false, true>},
          {launch_k_step<float, true, false>, launch_k_step<float, true, true>}}};
     table[fp32][rot][tauf](nb, st, descs, tiles, ntiles, bases, step_off, flips, flip);
+    return hipGetLastError();
+}
+
+hipError_t launch_column(const SolveDesc *desc, int nwaves, int64_t step0, int flip, int nk, bool fp32, bool tauf,
+                         hipStream_t st)
+{
+    const int nb = (nwaves + BLOCK / 64 - 1) / (BLOCK / 64);
+    if (nb == 0 || nk <= 0) return hipSuccess;
+    if (fp32) {
+        if (tauf)
+            hipLaunchKernelGGL((k_column<float, true>), dim3(nb), dim3(BLOCK), 0, st, desc, step0, flip, nk);
+        else
+            hipLaunchKernelGGL((k_column<float, false>), dim3(nb), dim3(BLOCK), 0, st, desc, step0, flip, nk);
+    } else {
+        if (tauf)
+            hipLaunchKernelGGL((k_column<double, true>), dim3(nb), dim3(BLOCK), 0, st, desc, step0, flip, nk);
+        else
+            hipLaunchKernelGGL((k_column<double, false>), dim3(nb), dim3(BLOCK), 0, st, desc, step0, flip, nk);
+    }
     return hipGetLastError();
 }
 

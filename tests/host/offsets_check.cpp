@@ -57,9 +57,35 @@ void check_grid(const Grid &g)
     const uint32_t es = (uint32_t)g.esz;
     const bool rotated = g.sector != 8;
     if (g.nt == 1) {
-        // single column: lanes along r (radial_block)
+        // single column, several steps per launch (k_column): every lane
+        // loads its row clamped to the grid, owned lanes store there, and
+        // every row is owned exactly once
+        std::vector<int> owners(g.nr, 0);
+        for (int t = 0; t * COL_W < g.nr; ++t)
+            for (int lane = 0; lane < 64; ++lane) {
+                const ColumnOffsets o = column_offsets(g.nr, b, t, lane);
+                if (o.own && o.row >= 0 && o.row < g.nr) ++owners[o.row];
+            }
+        for (int r = 0; r < g.nr; ++r) {
+            ++n_checked;
+            if (owners[r] != 1 && n_failed++ < 20) std::fprintf(stderr, "column row %d owned %d times\n", r, owners[r]);
+        }
+        for (int t = 0; t * COL_W < g.nr; ++t)
+            for (int lane = 0; lane < 64; ++lane) {
+                const ColumnOffsets o = column_offsets(g.nr, b, t, lane);
+                access(g, "column rest", 0, 0, o.vo, es, F, t, lane);
+                for (int c = 0; c < 16; ++c)
+                    access(g, "column pair", b.rest + (uint64_t)c * b.pair, b.rest + (uint32_t)c * b.pair, o.vo,
+                           2 * es, F, t, lane);
+                access(g, "column lambda", 0, 0, o.vol, 8, L, t, lane);
+                access(g, "column tau field", 0, 0, o.om, es, OM, t, lane);
+                if (o.own && (o.row < 0 || o.row >= g.nr)) {
+                    if (n_failed++ < 20) std::fprintf(stderr, "column lane %d of wavefront %d owns row %d\n", lane, t, o.row);
+                }
+            }
+        // single column, one step per launch in packs: lanes along r (radial_block)
         const bool disc = false;
-        for (int blk = 0; blk * 64 < g.nr; ++blk)
+        for (int blk = 0; blk * COL_W < g.nr; ++blk)
             for (int lane = 0; lane < 64; ++lane) {
                 const RadialOffsets o = radial_offsets(g.nr, pitch, disc, g.esz, b, blk, lane);
                 access(g, "radial rest", 0, 0, o.vo, es, F, blk, lane);

@@ -159,6 +159,12 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
         assert shifts >= 66, (name, shifts)
         assert dpp >= shifts, (name, dpp)
         assert _dpp_under_narrowed_exec(lines) == 0, name
+    # the multi-step single-column kernel: 2 precisions x the two kinds of tau
+    columns = list(_kernel_bodies(asm, "k_column"))
+    assert len(columns) == 4
+    for name, lines in columns:
+        assert sum(("wave_shr:1" in t or "wave_shl:1" in t) for t in lines) >= 66, name
+        assert _dpp_under_narrowed_exec(lines) == 0, name
 
 
 def test_narrowed_exec_check_finds_a_dpp_inside_a_branch():
@@ -180,13 +186,13 @@ def test_step_kernel_uses_no_scratch_memory():
     """Register spills of the step kernels must stay in registers (AGPRs): a
     spill to scratch memory inside the row loop adds memory round trips to
     every row.  Checked on the code-object metadata of every variant of the
-    one-step and the two-step kernel."""
+    one-step, the two-step and the single-column kernel."""
     asm = _step_kernels_asm()
     seen = 0
     for block in asm.split("- .agpr_count:")[1:]:
         name = re.search(r"\.name:\s+(\S+)", block).group(1)
-        if "k_step" not in name:
+        if "k_step" not in name and "k_column" not in name:
             continue
         seen += 1
         assert int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1)) == 0, name
-    assert seen == 12
+    assert seen == 16
