@@ -53,6 +53,12 @@
  *   R17 lambda is not clamped.
  *   R18 If the reaction is gated off or a+b = 0: lambda_reac = lambda.
  *
+ * Drift report (ora_diag): the paper defines none.  The sums are taken over
+ * the cells with the area weight r_i dr dtheta of the cell-centred grid:
+ * mass rho, energy rho T + rho |u|^2 / 2, chemical energy rho Q (1 - lambda);
+ * cells with a non-finite moment or lambda are counted and left out of the
+ * sums, and cells with rho <= 0 or T <= 0 are counted.
+ *
  * Per-cell relaxation time (Sec. IV, point (ii)): the paper says tau should
  * depend on the local state but gives no form, so the oracle takes a field
  * tau[ir][jt] as an input (ora_set_tau) and relaxes each cell with its own
