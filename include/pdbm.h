@@ -232,8 +232,9 @@ int pdbm_set_tau_async(pdbm_solver *s, const void *tau_device);
  * state it starts from.  Solves of the full annulus with ntheta > 1, in
  * either precision, take the steps two per launch (one pass over f for both;
  * the result equals that of single steps to rounding), and an odd count ends
- * with a single step; the states after every call are those of Sec. II.C's
- * scheme either way. */
+ * with a single step; solves with a single theta column take up to 8 steps
+ * per launch.  The states after every call are those of Sec. II.C's scheme
+ * either way. */
 int pdbm_step(pdbm_solver *s, int64_t nsteps);
 
 /* Number of steps taken so far (host-side counter). */
