@@ -371,7 +371,8 @@ bool Solve::fusable() const
 
 int Solve::reduce_records(hipStream_t st)
 {
-    if (step > red_to) HIPCHK(launch_records(dd, 1, nullptr, red_to, step, st));
+    // a solve that makes no records has no partial sums to add up
+    if (step > red_to && p.diag_every > 0) HIPCHK(launch_records(dd, 1, nullptr, red_to, step, st));
     red_to = step;
     return PDBM_OK;
 }
