@@ -7,9 +7,12 @@ forms advance two steps per pass over f (k_step2).
 
 Default workload: the 1024 x 1024 outward detonation in float64 (2000
 steps).  Prints one JSON line.  The float32 form of the same workload is
-timed alongside and reported under "fp32".
+timed alongside and reported under "fp32"; the packed parameter sweep and
+the served request stream under "packed_sweep" and "serving"; the off-step
+kernels (non-equilibrium measures, the step with a per-cell tau field)
+under "side_kernels".
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32] [--no-serving] [--no-side]
 """
 from __future__ import annotations
 
@@ -41,6 +44,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 form")
     ap.add_argument("--cpu-steps", type=int, default=400, help="oracle steps of the CPU sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the packed-batch and serving measurements")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the off-step kernels (non-equilibrium measures, per-cell tau field)")
     ap.add_argument("--batch-solves", type=int, default=256, help="solves of the packed parameter sweep")
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of each solve of the sweep")
     ap.add_argument("--serving-requests", type=int, default=1000,
@@ -216,6 +221,66 @@ def roofline(cells, dtype, ev_seconds, steps, kernel, steps_per_launch, traffic=
     return out
 
 
+def side_kernels(P, w, torch, steps=200, calls=20, warm_ms=60.0):
+    """The hot path's optional parts on the float64 workload, timed with HIP
+    events on the stream they run on, after `warm_ms` of throwaway steps
+    (clock_warmup):
+    - k_noneq, the non-equilibrium measures Delta*_m of every cell (Sec.
+      II.E): `calls` launches on the state after `steps` steps; it reads f
+      (33 x 8 B per cell) and writes 12 float64 measures (96 B);
+    - k_step2<double, TAUF>, the step with a per-cell relaxation time (Sec.
+      IV, point (ii)): `steps` steps with a uniform tau field against the
+      same steps of the plain solve, the two timed in turn twice (the
+      second pair is reported); the field adds 8 B read per cell per
+      launch."""
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    plain = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64, diag_every=1), P.make_ic(**w.ic_kw()),
+                     stream=stream)
+    tauf = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64, diag_every=1, flags=P.PDBM_TAU_FIELD),
+                    P.make_ic(**w.ic_kw()), stream=stream)
+    tauf.set_tau(None)  # every cell at the parameters' tau: the same steps as the plain solve
+    plain.step(20)
+    tauf.step(20)
+    clock_warmup(P, w, P.PDBM_FP64, warm_ms, torch)
+    for _ in range(2):
+        t_plain = timed(lambda: plain.step(steps))
+        t_tauf = timed(lambda: tauf.step(steps))
+    out_t = torch.empty((P.PDBM_NONEQ_N, w.nr, w.ntheta), dtype=torch.float64, device="cuda")
+    plain.noneq_async(out_t)
+    torch.cuda.synchronize()
+
+    def noneq_calls():
+        for _ in range(calls):
+            plain.noneq_async(out_t)
+
+    t_noneq = timed(noneq_calls) / calls
+    plain.close()
+    tauf.close()
+    nq_bytes = (33 * 8 + P.PDBM_NONEQ_N * 8) * w.cells
+    launches = steps / 2
+    per_launch = BYTES_PER_CELL["f64"] * w.cells * 2
+    return {
+        "noneq": {"kernel": "k_noneq<double>", "calls": calls, "avg_us": round(t_noneq * 1e6, 2),
+                  "bytes_per_call": nq_bytes, "achieved_gbs": round(nq_bytes / t_noneq / 1e9, 1),
+                  "frac_of_peak": round(nq_bytes / t_noneq / 1e9 / HBM_PEAK_GBS, 4)},
+        "tau_field": {"kernel": "k_step2<double, TAUF>", "steps": steps,
+                      "avg_launch_us": round(t_tauf / launches * 1e6, 2),
+                      "plain_avg_launch_us": round(t_plain / launches * 1e6, 2),
+                      "extra_bytes_per_launch": 8 * w.cells,
+                      "effective_gbs": round(per_launch / (t_tauf / launches) / 1e9, 1),
+                      "effective_frac_of_peak": round(per_launch / (t_tauf / launches) / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+
+
 def packed_sweep(P, W, torch, count, nsteps):
     """Independent float32 solves of the parameter sweep advanced together in
     packed, graph-captured launches (chunks of 50 steps)."""
@@ -388,6 +453,8 @@ def main():
             served, serial = serving_stream(P, W, torch, a.serving_requests, sweep["value"])
             out["serving"] = {"served_fp32": served, "serial_fp64": serial,
                               "workload": f"poisson{a.serving_requests}_logU"}
+    if not a.no_side:
+        out["side_kernels"] = side_kernels(P, w, torch, warm_ms=a.clock_warmup_ms)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out))

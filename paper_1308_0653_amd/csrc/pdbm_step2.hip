@@ -67,6 +67,18 @@ struct LaneDiag {
     __device__ __forceinline__ double total(int i) const { return wave_sum(red[i]); }
 };
 
+// Whether march2 loads the per-cell exp(-dt/tau) of a row a pass before the
+// row's stage A needs it.  In float64, one wavefront per SIMD has nothing to
+// run while a load made at the point of use is in flight: loaded there, the
+// field cost 7 us per launch (162.4 against 155.2 us), loaded ahead 0.8 us.
+// Float32's second wavefront covers that wait, and the register held through
+// the pass made it slower (97.5 against 96.5 us per launch).
+template <typename real, bool TAUF>
+__device__ __forceinline__ constexpr bool omega_ahead()
+{
+    return TAUF && sizeof(real) == 8;
+}
+
 // One row of one of the two steps: the arithmetic of update_row, with the
 // azimuthal halo from H.  Radial neighbours: the row behind in compact LDS
 // slots (of each opposite pair of directions only the one that takes its
@@ -83,10 +95,17 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
                                           double lc,
                                           double lahead, const bool mr[4], const bool mt[4], const real acr[4],
                                           const real ctv[4], bool lr_behind, double csx, double csy, double &lout,
-                                          Diag &D, bool diag)
+                                          real om, Diag &D, bool diag)
 {
     const DescPtr dp = S.dp;
-    const Cell<real> C(dp, fc, lc, omega_at<real, TAUF>(dp, S.vo, (uint32_t)ir * S.rest_bytes));
+    // the cell's exp(-dt/tau); in float64 with TAUF `om`, loaded by march2 a
+    // pass ahead
+    real omega;
+    if constexpr (omega_ahead<real, TAUF>())
+        omega = om;
+    else
+        omega = omega_at<real, TAUF>(dp, S.vo, (uint32_t)ir * S.rest_bytes);
+    const Cell<real> C(dp, fc, lc, omega);
     const double ri = dp->r_min + ((double)ir + 0.5) * dp->dr;
     const real kt = (real)(dp->dt_dth / ri);
     real act[4], aa[4];
@@ -460,6 +479,11 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
         edge_cells<real, TAUF, 2>(S, strip, i0, i1, ef, el);
     load_first_rows();
     fill_behind(fb, t, mr, lane);
+    // omega_ahead: exp(-dt/tau) of stage A's row (oa), loaded a pass ahead,
+    // and of stage B's (ob), the row stage A had a pass before
+    real oa = (real)0, ob = (real)0;
+    if constexpr (omega_ahead<real, TAUF>())
+        oa = omega_at<real, true>(dp, S.vo, (uint32_t)(vlo ? rbefore : first) * S.rest_bytes);
     wave_lds_sync();
 
     for (int p = p0; p <= count; ++p) {
@@ -487,7 +511,7 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
             wave_lds_sync();
             const LdsHalo<real> H{hb, hbl};
             stage_row<real, true, TAUF>(S, ir, fb, fc, fn, ga, gc, H, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y,
-                                        gln, DA, diagA && p >= 0 && p < count);
+                                        gln, oa, DA, diagA && p >= 0 && p < count);
         } else {
             // beyond the last grid row: the zero-gradient ghost of g
 #pragma unroll
@@ -497,6 +521,12 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
         // f at position p + 2 (the row ahead of the next stage A) replaces f(p)
         if (p + 1 < count || (p + 1 == count && vhi)) row_or_ghost(S, ir + 2 * step, fc, lx, fn, ln);
         if (p + 2 < count || (p + 2 == count && vhi)) S.load_halo(ir + 2 * step, hx.h, hx.hl);
+        // the next stage A's exp(-dt/tau), where that stage runs on a grid row
+        const real oa_used = oa;
+        if constexpr (omega_ahead<real, TAUF>()) {
+            if (p + 1 < count || (p + 1 == count && vhi))
+                oa = omega_at<real, true>(dp, S.vo, (uint32_t)(ir + step) * S.rest_bytes);
+        }
         // (B) second step at position p - 1
         if (p == 0 && !vlo) {
             // the row behind stage B's first row is the (zero-gradient)
@@ -512,7 +542,7 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
             const EdgeHalo<real> H{ef[0][e], ef[1][e], el[0][e], el[1][e]};
             double unused;
             stage_row<real, false, TAUF>(S, ir - step, gb, gc, nullptr, ga, nullptr, H, glp, glc, gln, mr, mt, acr, ctv,
-                                         !down, cs.x, cs.y, unused, DB, diagB);
+                                         !down, cs.x, cs.y, unused, ob, DB, diagB);
         }
         if constexpr (sizeof(real) == 4) {
             swap_rows(fc, fn);
@@ -526,6 +556,7 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
                 fn[q] = t;
             }
         }
+        ob = oa_used;
         hc = hn;
         hn = hx;
         lp = lc;
