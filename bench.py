@@ -8,9 +8,9 @@ forms advance two steps per pass over f (k_step2).
 Default workload: the 1024 x 1024 outward detonation in float64 (2000
 steps).  Prints one JSON line.  The float32 form of the same workload is
 timed alongside and reported under "fp32"; the packed parameter sweep and
-the served request stream under "packed_sweep" and "serving"; the off-step
-kernels (non-equilibrium measures, the step with a per-cell tau field)
-under "side_kernels".
+the served request stream under "packed_sweep" and "serving"; the other
+kernels of the path (non-equilibrium measures, the step with a per-cell tau
+field, one step of a rotated sector) under "side_kernels".
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32] [--no-serving] [--no-side]
 """
@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=400, help="oracle steps of the CPU sample")
     ap.add_argument("--no-serving", action="store_true", help="skip the packed-batch and serving measurements")
     ap.add_argument("--no-side", action="store_true",
-                    help="skip the off-step kernels (non-equilibrium measures, per-cell tau field)")
+                    help="skip the other kernels (non-equilibrium measures, per-cell tau field, rotated sector)")
     ap.add_argument("--batch-solves", type=int, default=256, help="solves of the packed parameter sweep")
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of each solve of the sweep")
     ap.add_argument("--serving-requests", type=int, default=1000,
@@ -232,7 +232,11 @@ def side_kernels(P, w, torch, steps=200, calls=20, warm_ms=60.0):
       IV, point (ii)): `steps` steps with a uniform tau field against the
       same steps of the plain solve, the two timed in turn twice (the
       second pair is reported); the field adds 8 B read per cell per
-      launch."""
+      launch;
+    - k_step<double, ROT>, one step per launch of a rotated sector (Sec.
+      II.D: the periodic images of a sector turn the directions): the same
+      gas on half the annulus (sector 4, 1024 x 512 cells, the same dtheta),
+      `steps` steps."""
     stream = torch.cuda.current_stream()
 
     def timed(fn):
@@ -265,6 +269,13 @@ def side_kernels(P, w, torch, steps=200, calls=20, warm_ms=60.0):
     t_noneq = timed(noneq_calls) / calls
     plain.close()
     tauf.close()
+    kw = w.params_kw()
+    kw.update(sector=4, ntheta=w.ntheta // 2)
+    half = P.Solver(P.make_params(**kw, precision=P.PDBM_FP64, diag_every=1), P.make_ic(**w.ic_kw()), stream=stream)
+    half.step(20)
+    t_half = timed(lambda: half.step(steps))
+    half.close()
+    half_cells = w.nr * (w.ntheta // 2)
     nq_bytes = (33 * 8 + P.PDBM_NONEQ_N * 8) * w.cells
     launches = steps / 2
     per_launch = BYTES_PER_CELL["f64"] * w.cells * 2
@@ -278,6 +289,11 @@ def side_kernels(P, w, torch, steps=200, calls=20, warm_ms=60.0):
                       "extra_bytes_per_launch": 8 * w.cells,
                       "effective_gbs": round(per_launch / (t_tauf / launches) / 1e9, 1),
                       "effective_frac_of_peak": round(per_launch / (t_tauf / launches) / 1e9 / HBM_PEAK_GBS, 4)},
+        "sector": {"kernel": "k_step<double, ROT>", "sector": 4, "nr": w.nr, "ntheta": w.ntheta // 2, "steps": steps,
+                   "avg_launch_us": round(t_half / steps * 1e6, 2),
+                   "achieved_gbs": round(BYTES_PER_CELL["f64"] * half_cells / (t_half / steps) / 1e9, 1),
+                   "frac_of_peak": round(BYTES_PER_CELL["f64"] * half_cells / (t_half / steps) / 1e9 / HBM_PEAK_GBS,
+                                         4)},
     }
 
 

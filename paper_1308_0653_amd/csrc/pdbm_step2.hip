@@ -67,18 +67,6 @@ struct LaneDiag {
     __device__ __forceinline__ double total(int i) const { return wave_sum(red[i]); }
 };
 
-// Whether march2 loads the per-cell exp(-dt/tau) of a row a pass before the
-// row's stage A needs it.  In float64, one wavefront per SIMD has nothing to
-// run while a load made at the point of use is in flight: loaded there, the
-// field cost 7 us per launch (162.4 against 155.2 us), loaded ahead 0.8 us.
-// Float32's second wavefront covers that wait, and the register held through
-// the pass made it slower (97.5 against 96.5 us per launch).
-template <typename real, bool TAUF>
-__device__ __forceinline__ constexpr bool omega_ahead()
-{
-    return TAUF && sizeof(real) == 8;
-}
-
 // One row of one of the two steps: the arithmetic of update_row, with the
 // azimuthal halo from H.  Radial neighbours: the row behind in compact LDS
 // slots (of each opposite pair of directions only the one that takes its
@@ -98,10 +86,9 @@ __device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, r
                                           real om, Diag &D, bool diag)
 {
     const DescPtr dp = S.dp;
-    // the cell's exp(-dt/tau); in float64 with TAUF `om`, loaded by march2 a
-    // pass ahead
+    // the cell's exp(-dt/tau): with TAUF `om`, loaded by march2 a pass ahead
     real omega;
-    if constexpr (omega_ahead<real, TAUF>())
+    if constexpr (TAUF)
         omega = om;
     else
         omega = omega_at<real, TAUF>(dp, S.vo, (uint32_t)ir * S.rest_bytes);
@@ -477,13 +464,16 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
         edge_cells<real, TAUF, 4>(S, strip, i0, i1, ef, el);
     else
         edge_cells<real, TAUF, 2>(S, strip, i0, i1, ef, el);
+    // TAUF: exp(-dt/tau) of stage A's row (oa), loaded a pass ahead, and of
+    // stage B's (ob), the row stage A had a pass before (loaded at the point
+    // of use, the field cost 7.2 us per float64 launch and 4.2 us per float32
+    // one; loaded ahead, 0.8 and 2.3 us)
+    real oa = (real)0, ob = (real)0;
+    if constexpr (TAUF)
+        oa = omega_at<real, true>(dp, S.vo, (uint32_t)(vlo ? rbefore : first) * S.rest_bytes);
     load_first_rows();
     fill_behind(fb, t, mr, lane);
-    // omega_ahead: exp(-dt/tau) of stage A's row (oa), loaded a pass ahead,
-    // and of stage B's (ob), the row stage A had a pass before
-    real oa = (real)0, ob = (real)0;
-    if constexpr (omega_ahead<real, TAUF>())
-        oa = omega_at<real, true>(dp, S.vo, (uint32_t)(vlo ? rbefore : first) * S.rest_bytes);
+    if constexpr (TAUF) settle(oa);
     wave_lds_sync();
 
     for (int p = p0; p <= count; ++p) {
@@ -523,7 +513,7 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
         if (p + 2 < count || (p + 2 == count && vhi)) S.load_halo(ir + 2 * step, hx.h, hx.hl);
         // the next stage A's exp(-dt/tau), where that stage runs on a grid row
         const real oa_used = oa;
-        if constexpr (omega_ahead<real, TAUF>()) {
+        if constexpr (TAUF) {
             if (p + 1 < count || (p + 1 == count && vhi))
                 oa = omega_at<real, true>(dp, S.vo, (uint32_t)(ir + step) * S.rest_bytes);
         }
