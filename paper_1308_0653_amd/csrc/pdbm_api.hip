@@ -61,9 +61,8 @@ Layout pdbm::layout_of(const pdbm_params &p, int rows)
     L.wpart = align256((size_t)PART_RING * L.nwaves * 5 * sizeof(double));
     L.hist = align256((size_t)(HIST_CAP + 1) * sizeof(pdbm_diag));
     L.cpart = align256((size_t)L.cblocks * 5 * sizeof(double));
-    L.counter = 256;
     L.state_total = 2 * L.f + 2 * L.lam + L.omega;
-    L.aux_total = L.cs + L.desc + L.state + L.wpart + L.hist + L.cpart + L.counter;
+    L.aux_total = L.cs + L.desc + L.state + L.wpart + L.hist + L.cpart;
     L.total = L.state_total + L.aux_total;
     return L;
 }
@@ -275,7 +274,6 @@ int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_
     hd.wpart = (double *)take(L.wpart);
     hd.hist = (pdbm_diag *)take(L.hist);
     cpart = (double *)take(L.cpart);
-    counter = (unsigned *)take(L.counter);
 
     hd.nr = p.nr;
     hd.nt = p.ntheta;
@@ -322,7 +320,6 @@ int Solve::init(const pdbm_params &pp, const pdbm_ic *ic, void *workspace, size_
     zero_state = SolveState{0};
     HIPCHK(hipMemcpyAsync(dd, &hd, sizeof hd, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(hd.state, &zero_state, sizeof zero_state, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemsetAsync(counter, 0, sizeof(unsigned), st));
     pdbm_ic uni;
     if (!ic) {
         std::memset(&uni, 0, sizeof uni);
@@ -381,11 +378,8 @@ int Solve::moments(double *out, pdbm_diag *diag_dev, hipStream_t st) const
 {
     DiagCtl c;
     c.partials = cpart;
-    c.counter = counter;
     c.out = diag_dev;
     c.step = step;
-    c.enabled = 1;
-    c.pad = 0;
     HIPCHK(launch_moments(hd, cur(), fp32, out, c, st));
     return PDBM_OK;
 }

@@ -41,7 +41,28 @@ __global__ __launch_bounds__(BLOCK) void k_moments(SolveDesc d, int cur, double 
         const double ri = d.r_min + ((double)ir + 0.5) * d.dr;
         diag_cell(red, rd, ux, uy, T, (double)e, lam, ri * d.dr * d.dth, d.Q);
     }
-    diag_reduce(dc, red, blockIdx.x, nb);
+    diag_partial(dc, red, blockIdx.x);
+}
+
+// The drift record of k_moments: one block adds the nb per-block partial
+// sums in a fixed order (deterministic, no floating-point atomics).
+__global__ __launch_bounds__(BLOCK) void k_diag_final(DiagCtl dc, int nb)
+{
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += BLOCK)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i] += dc.partials[5 * (size_t)b + i];
+    block_sum5(acc);
+    if (threadIdx.x == 0) {
+        pdbm_diag r;
+        r.step = dc.step;
+        r.mass = acc[0];
+        r.energy = acc[1];
+        r.chem = acc[2];
+        r.n_nonfinite = (int64_t)acc[3];
+        r.n_nonphys = (int64_t)acc[4];
+        *dc.out = r;
+    }
 }
 
 // ----------------------------------------------------- non-equilibrium --
@@ -215,6 +236,7 @@ hipError_t launch_moments(const SolveDesc &d, int cur, bool fp32, double *out, c
         hipLaunchKernelGGL(k_moments<float>, dim3(nb), dim3(BLOCK), 0, st, d, cur, out, dc);
     else
         hipLaunchKernelGGL(k_moments<double>, dim3(nb), dim3(BLOCK), 0, st, d, cur, out, dc);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(BLOCK), 0, st, dc, nb);
     return hipGetLastError();
 }
 

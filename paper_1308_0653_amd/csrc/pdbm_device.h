@@ -241,40 +241,19 @@ __device__ __forceinline__ void block_sum5(double v[5])
         }
 }
 
-// Per-block partial sums, then the last block to finish adds the partials in
-// a fixed order (deterministic, no floating-point atomics) and writes the
-// record.  Must be reached by every thread of every block.
-__device__ void diag_reduce(const DiagCtl &dc, double v[5], int tile, int nb)
+// Per-block partial sums of the drift report, written to dc.partials[tile];
+// a second launch (k_diag_final) adds them up.  Must be reached by every
+// thread of every block.  (A version in one kernel, where the last block to
+// finish added the partials, needed a device-wide release per block, which
+// on this GPU writes back the L2 of the block's die: the moments of a
+// 1024 x 1024 float64 state took 268 us there, 64 + 7 us in two launches.)
+__device__ __forceinline__ void diag_partial(const DiagCtl &dc, double v[5], int tile)
 {
-    __shared__ int last;
     block_sum5(v);
     if (threadIdx.x == 0) {
         double *p = dc.partials + 5 * (size_t)tile;
 #pragma unroll
         for (int i = 0; i < 5; ++i) p[i] = v[i];
-        __threadfence();
-        const unsigned done = atomicAdd(dc.counter, 1u);
-        last = done == (unsigned)(nb - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nb; b += BLOCK)
-#pragma unroll
-        for (int i = 0; i < 5; ++i)
-            acc[i] += __hip_atomic_load(dc.partials + 5 * (size_t)b + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    block_sum5(acc);
-    if (threadIdx.x == 0) {
-        pdbm_diag r;
-        r.step = dc.step;
-        r.mass = acc[0];
-        r.energy = acc[1];
-        r.chem = acc[2];
-        r.n_nonfinite = (int64_t)acc[3];
-        r.n_nonphys = (int64_t)acc[4];
-        *dc.out = r;
-        __hip_atomic_store(dc.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

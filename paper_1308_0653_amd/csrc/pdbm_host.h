@@ -32,7 +32,7 @@ constexpr int ONE_STEP_BATCH_ROWS = 4;
 // (theta table, description, step state, drift partial sums and records,
 // moments reduction scratch).
 struct Layout {
-    size_t f, lam, omega, cs, desc, state, wpart, hist, cpart, counter, total;  // omega: per-cell relaxation factors (0 without PDBM_TAU_FIELD)
+    size_t f, lam, omega, cs, desc, state, wpart, hist, cpart, total;  // omega: per-cell relaxation factors (0 without PDBM_TAU_FIELD)
     size_t state_total, aux_total;  // total = state_total + aux_total
     int pitch, rows, nwaves, cblocks;
     size_t esz;
@@ -56,7 +56,6 @@ class Solve {
     SolveDesc hd{};           // host copy, pointers filled in
     SolveDesc *dd = nullptr;  // device copy read by the step kernel
     double *cpart = nullptr;  // moments-kernel reduction scratch
-    unsigned *counter = nullptr;
     int64_t step = 0;      // steps taken (never beyond hd.nsteps)
     int flip = 0;          // the current state is in buffer (step + flip) & 1 (two-step launches toggle it)
     int64_t rec_from = 0;  // drift records are valid from this step on

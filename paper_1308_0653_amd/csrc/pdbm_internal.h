@@ -64,12 +64,9 @@ struct SolveDesc {
 
 // Block-level drift reduction of the cell kernels (moments).
 struct DiagCtl {
-    double *partials;   // [nblocks][5]
-    unsigned *counter;  // blocks finished, reset by the last one
-    pdbm_diag *out;     // where the final record goes
-    int64_t step;       // step count of the reduced state
-    int32_t enabled;
-    int32_t pad;
+    double *partials;  // [nblocks][5]
+    pdbm_diag *out;    // where the final record goes
+    int64_t step;      // step count of the reduced state
 };
 
 // Kernel launchers (pdbm_step.hip, pdbm_step2.hip, pdbm_cells.hip).  All enqueue on `st` and return the
