@@ -812,9 +812,7 @@ __device__ __forceinline__ void march(DescPtr dp, const StepBufs &bufs, int stri
     real fc[NQ], fn[NQ], fnn[NQ], hc[2], hn[2], hnn[2];
     double lp, lc, ln, lnn, hlc, hln, hlnn;
     // TAUF: exp(-dt/tau) of the row computed (oc) and of the next (on),
-    // loaded a row ahead (at the point of use the load held up the
-    // wavefront: a 1024 x 512 float64 sector took 69.0 against 63.8 us per
-    // step)
+    // loaded a row ahead so that the wavefront does not wait for it
     real oc = (real)0, on = (real)0;
     if constexpr (TAUF) oc = omega_at<real, true>(dp, S.vo, (uint32_t)first * S.rest_bytes);
     S.load_row(first, fc, lc);
