@@ -10,7 +10,7 @@ steps).  Prints one JSON line.  The float32 form of the same workload is
 timed alongside and reported under "fp32"; the packed parameter sweep and
 the served request stream under "packed_sweep" and "serving"; the other
 kernels of the path (non-equilibrium measures, the step with a per-cell tau
-field, one step of a rotated sector) under "side_kernels".
+field, a rotated sector) under "side_kernels".
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32] [--no-serving] [--no-side]
 """
@@ -233,7 +233,7 @@ def side_kernels(P, w, torch, steps=200, calls=20, warm_ms=60.0):
       same steps of the plain solve, the two timed in turn twice (the
       second pair is reported); the field adds 8 B read per cell per
       launch;
-    - k_step<double, ROT>, one step per launch of a rotated sector (Sec.
+    - k_step2<double, ROT>, two steps per launch of a rotated sector (Sec.
       II.D: the periodic images of a sector turn the directions): the same
       gas on half the annulus (sector 4, 1024 x 512 cells, the same dtheta),
       `steps` steps."""
@@ -289,11 +289,11 @@ def side_kernels(P, w, torch, steps=200, calls=20, warm_ms=60.0):
                       "extra_bytes_per_launch": 8 * w.cells,
                       "effective_gbs": round(per_launch / (t_tauf / launches) / 1e9, 1),
                       "effective_frac_of_peak": round(per_launch / (t_tauf / launches) / 1e9 / HBM_PEAK_GBS, 4)},
-        "sector": {"kernel": "k_step<double, ROT>", "sector": 4, "nr": w.nr, "ntheta": w.ntheta // 2, "steps": steps,
-                   "avg_launch_us": round(t_half / steps * 1e6, 2),
-                   "achieved_gbs": round(BYTES_PER_CELL["f64"] * half_cells / (t_half / steps) / 1e9, 1),
-                   "frac_of_peak": round(BYTES_PER_CELL["f64"] * half_cells / (t_half / steps) / 1e9 / HBM_PEAK_GBS,
-                                         4)},
+        "sector": {"kernel": "k_step2<double, ROT>", "sector": 4, "nr": w.nr, "ntheta": w.ntheta // 2, "steps": steps,
+                   "steps_per_launch": 2, "avg_launch_us": round(t_half / launches * 1e6, 2),
+                   "effective_gbs": round(BYTES_PER_CELL["f64"] * half_cells / (t_half / steps) / 1e9, 1),
+                   "effective_frac_of_peak": round(
+                       BYTES_PER_CELL["f64"] * half_cells / (t_half / steps) / 1e9 / HBM_PEAK_GBS, 4)},
     }
 
 

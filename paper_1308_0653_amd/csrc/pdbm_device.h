@@ -537,6 +537,28 @@ struct Strip {
     }
 };
 
+// (cos, sin) of an angle turned by m pi / 4: the angle of a periodic image
+// of a rotated sector, m sector widths on, from that of its physical column.
+__device__ __forceinline__ double2 turn_cs(double2 cs, int m)
+{
+    double c = cs.x, s = cs.y;
+    if (m & 1) {
+        const double c1 = SQH * (c - s), s1 = SQH * (c + s);
+        c = c1;
+        s = s1;
+    }
+    if (m & 2) {
+        const double c1 = -s;
+        s = c;
+        c = c1;
+    }
+    if (m & 4) {
+        c = -c;
+        s = -s;
+    }
+    return make_double2(c, s);
+}
+
 // Wave-uniform copy of lane l of v.
 __device__ __forceinline__ float lane_value(float v, int l)
 {

@@ -95,11 +95,11 @@ hipError_t launch_column(const SolveDesc *desc, int nwaves, int64_t step0, int f
 // step_off, flips and flip as launch_step): reads buffer (s + flip_i) & 1 and
 // writes the other one, so the caller toggles flip_i.  A solve with one step
 // left, or every solve with `single`, takes one step and keeps its parity.
-// Full annulus only (no rotated sector images), ntheta > 1, rows per
-// wavefront at most FUSE_ROWS.  Makes the drift records of the steps it
-// takes as launch_step does; `tauf` as launch_step.
+// ntheta > 1, rows per wavefront at most FUSE_ROWS, no disc; `rot` selects
+// the variant for sectors other than the full annulus.  Makes the drift
+// records of the steps it takes as launch_step does; `tauf` as launch_step.
 hipError_t launch_step2(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases,
-                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, bool tauf,
+                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, bool tauf, bool rot,
                         hipStream_t st);
 // Per-cell relaxation factors omegaf[i][j] = exp(-dt / tau[i * nt + j]) from
 // a dense float64 tau field in device memory, or all equal to `uniform`

@@ -94,13 +94,21 @@ __host__ __device__ inline StripOffsets strip_offsets(int nt, int64_t pitch, int
     return o;
 }
 
+// floor(c / n) for n > 0: the periodic image a strip column c belongs to.
+__host__ __device__ constexpr int wraps_of(int c, int n) { return c >= 0 ? c / n : -((n - 1 - c) / n); }
+
 // Cells of the two-step kernel's strip edges (edge_cells in pdbm_step2.hip):
 // lane 32 side + 2 e + h takes row r of the column bordering strip `strip`
 // on `side` (0: left, 1: right) and gathers the cell (row r, column pc), its
 // radial neighbours (rows rlo, rhi: zero-gradient ghosts at the ends) and
-// its azimuthal neighbours (columns pl, pr).
+// its azimuthal neighbours (columns pl, pr).  Those columns, in the strip's
+// own numbering, may be periodic images: in a rotated sector their data has
+// its directions turned (tc, tl, tr, as `rot` in strip_offsets), and the
+// cell's and lane 0 / 63's angles are those of the physical columns pc and
+// pk turned by the sector (tc, tk).
 struct EdgeOffsets {
     int pc, pl, pr, pk;            // the cell's column, its left and right neighbours, the column of lane 0 / 63
+    int tc, tl, tr, tk;            // direction shifts of the data of those columns in the strip's frame
     int rlo, rhi;                  // rows of its radial neighbours
     uint32_t orow, olo, ohi;       // row offsets of f: the cell's row and its radial neighbours
     uint32_t cc, cl, cr;           // pair-column offsets of f: pc, pl, pr
@@ -108,15 +116,29 @@ struct EdgeOffsets {
     uint32_t lc, lb, la, lL, lR;   // lambda: the cell, below, above, left, right
     uint32_t om;                   // the cell's entry of the per-cell tau field
 };
-__host__ __device__ inline EdgeOffsets edge_offsets(int nr, int nt, int esz, const RowBytes &b, int strip, int side,
-                                                    int r)
+__host__ __device__ inline EdgeOffsets edge_offsets(int nr, int nt, int sector, bool rotated, int esz,
+                                                    const RowBytes &b, int strip, int side, int r)
 {
     EdgeOffsets o;
     const int c0 = strip * STRIP;
-    o.pc = side == 0 ? (c0 + nt - 1) % nt : (c0 + STRIP) % nt;
-    o.pl = (o.pc + nt - 1) % nt;
-    o.pr = (o.pc + 1) % nt;
-    o.pk = (side == 0 ? c0 : c0 + STRIP - 1) % nt;
+    if (!rotated) {
+        o.pc = side == 0 ? (c0 + nt - 1) % nt : (c0 + STRIP) % nt;
+        o.pl = (o.pc + nt - 1) % nt;
+        o.pr = (o.pc + 1) % nt;
+        o.pk = (side == 0 ? c0 : c0 + STRIP - 1) % nt;
+        o.tc = o.tl = o.tr = o.tk = ROT_NONE;
+    } else {
+        const int c = side == 0 ? c0 - 1 : c0 + STRIP, k = side == 0 ? c0 : c0 + STRIP - 1;  // strip numbering
+        const int wc = wraps_of(c, nt), wl = wraps_of(c - 1, nt), wr = wraps_of(c + 1, nt), wk = wraps_of(k, nt);
+        o.pc = c - wc * nt;
+        o.pl = (c - 1) - wl * nt;
+        o.pr = (c + 1) - wr * nt;
+        o.pk = k - wk * nt;
+        o.tc = (-wc * sector) & 7;
+        o.tl = (-wl * sector) & 7;
+        o.tr = (-wr * sector) & 7;
+        o.tk = (-wk * sector) & 7;
+    }
     o.rlo = r - 1 < 0 ? 0 : r - 1;
     o.rhi = r + 1 > nr - 1 ? nr - 1 : r + 1;
     const uint32_t es = (uint32_t)esz;

@@ -179,9 +179,9 @@ class Pack {
         hipError_t e = hipSuccess;
         if (pairs) {
             for (int i = 0; 2 * i + 1 < n && e == hipSuccess; ++i)
-                e = launch_step2(ddescs, dtiles, ntiles, dbases, 2 * i, dflips, i & 1, false, fp32, false, st);
+                e = launch_step2(ddescs, dtiles, ntiles, dbases, 2 * i, dflips, i & 1, false, fp32, false, false, st);
             if (e == hipSuccess && (n & 1))
-                e = launch_step2(ddescs, dtiles, ntiles, dbases, n - 1, dflips, (n / 2) & 1, true, fp32, false, st);
+                e = launch_step2(ddescs, dtiles, ntiles, dbases, n - 1, dflips, (n / 2) & 1, true, fp32, false, false, st);
         } else {
             for (int i = 0; i < n && e == hipSuccess; ++i)
                 e = launch_step(ddescs, dtiles, ntiles, dbases, i, dflips, 0, fp32, rot, false, st);

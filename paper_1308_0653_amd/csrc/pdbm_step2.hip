@@ -1,6 +1,7 @@
-// Two time steps per launch, in one pass over f (k_step2): single solves of
-// the full annulus with more than one theta column, in float64 (one
-// wavefront per SIMD) and float32 (two).
+// Two time steps per launch, in one pass over f (k_step2): solves with more
+// than one theta column, full annuli (single or packed) and single rotated
+// sectors that are no disc, in float64 (one wavefront per SIMD) and float32
+// (two).
 #include "pdbm_device.h"
 
 namespace pdbm {
@@ -77,8 +78,8 @@ struct LaneDiag {
 // replaces in `ga` to `gold`, plane by plane, so that the registers of the
 // old row fill as those of fc empty; otherwise it is stored, for the strip's
 // own columns.
-template <typename real, bool STAGEA, bool TAUF, class Halo, class Diag>
-__device__ __forceinline__ void stage_row(const Strip<real, false> &S, int ir, real (*behind)[64], const real fc[NQ],
+template <typename real, bool STAGEA, bool TAUF, bool ROT, class Halo, class Diag>
+__device__ __forceinline__ void stage_row(const Strip<real, ROT> &S, int ir, real (*behind)[64], const real fc[NQ],
                                           const real *fn, real (*ga)[64], real *gold, const Halo &H, double lbehind,
                                           double lc,
                                           double lahead, const bool mr[4], const bool mt[4], const real acr[4],
@@ -221,8 +222,8 @@ __device__ __forceinline__ T cell_sum(T v)
 // directions as stage A of the strip owning the column does.  The first
 // lane of a cell keeps lambda.  Every lane runs every instruction up to the
 // final stores (the moment exchange is a lane permutation).
-template <typename real, bool TAUF, int LPC>
-__device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int strip, int i0, int i1,
+template <typename real, bool TAUF, int LPC, bool ROT>
+__device__ __forceinline__ void edge_cells(const Strip<real, ROT> &S, int strip, int i0, int i1,
                                            real (*ef)[FUSE_ROWS][16], double (*el)[FUSE_ROWS])
 {
     static_assert(LPC == 2 || LPC == 4, "two or four lanes per cell");
@@ -237,8 +238,13 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     // the cell, its radial neighbours (below row 0 the copy of row 0, above
     // row nr - 1 the copy of row nr - 1: zero-gradient ghosts; the two-step
     // kernel takes no disc) and its azimuthal neighbours
-    const EdgeOffsets o = edge_offsets(nr, nt, (int)sizeof(real), rb, strip, side, r);
-    const double2 cs = dp->cs[o.pc], ck = dp->cs[o.pk];
+    const EdgeOffsets o = edge_offsets(nr, nt, dp->sector, ROT, (int)sizeof(real), rb, strip, side, r);
+    double2 cs = dp->cs[o.pc], ck = dp->cs[o.pk];
+    if constexpr (ROT) {
+        // periodic images of a rotated sector: the angles turned by the sector
+        cs = turn_cs(cs, (8 - o.tc) & 7);
+        ck = turn_cs(ck, (8 - o.tk) & 7);
+    }
     const real cth = (real)cs.x, sth = (real)cs.y;
     const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
     const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
@@ -258,6 +264,38 @@ __device__ __forceinline__ void edge_cells(const Strip<real, false> &S, int stri
     for (int i = 0; i < NP; ++i) {
         const uint32_t po = pair_in_row(rb, NP * h + i);
         const int dd = i & 3;
+        if constexpr (ROT) {
+            second[i] = (kctv[dd] >= (real)0) == (side == 1);
+            const bool low = (crv[dd] >= (real)0) != second[i], left = (ctv[dd] >= (real)0) != second[i];
+            // each column's data has its directions turned by its shift t:
+            // direction dd (dd + 4) of this strip's frame is in the pair of
+            // (dd + t) % 4 of the same speed, the members swapped where
+            // (dd + t) % 8 >= 4
+            const int kb = (NP * h + i) & ~3;
+            const uint32_t pc = pair_in_row(rb, kb + ((dd + o.tc) & 3));
+            const uint32_t pl = pair_in_row(rb, kb + ((dd + o.tl) & 3));
+            const uint32_t pr = pair_in_row(rb, kb + ((dd + o.tr) & 3));
+            const bool sc = ((dd + o.tc) & 4) != 0, sl = ((dd + o.tl) & 4) != 0, sr = ((dd + o.tr) & 4) != 0;
+            real a, b;
+            bload2(a, b, S.fin, o.orow + o.cc + pc, 0u);
+            x[i] = sc ? b : a;
+            x[i + NP] = sc ? a : b;
+            const bool mc = second[i] != sc, mlr = left ? second[i] != sl : second[i] != sr;
+            if constexpr (sizeof(real) == 4) {
+                bload(nbr[i], S.fin, (low ? o.olo : o.ohi) + o.cc + pc + (mc ? (uint32_t)sizeof(real) : 0u), 0u);
+                bload(nbt[i], S.fin, o.orow + (left ? o.cl + pl : o.cr + pr) + (mlr ? (uint32_t)sizeof(real) : 0u),
+                      0u);
+            } else {
+                real lo0, lo1, hi0, hi1, l0, l1, r0, r1;
+                bload2(lo0, lo1, S.fin, o.olo + o.cc + pc, 0u);
+                bload2(hi0, hi1, S.fin, o.ohi + o.cc + pc, 0u);
+                bload2(l0, l1, S.fin, o.orow + o.cl + pl, 0u);
+                bload2(r0, r1, S.fin, o.orow + o.cr + pr, 0u);
+                nbr[i] = mc ? (low ? lo1 : hi1) : (low ? lo0 : hi0);
+                nbt[i] = left ? (mlr ? l1 : l0) : (mlr ? r1 : r0);
+            }
+            continue;
+        }
         bload2(x[i], x[i + NP], S.fin, o.orow + o.cc + po, 0u);
         second[i] = (kctv[dd] >= (real)0) == (side == 1);
         const bool low = (crv[dd] >= (real)0) != second[i], left = (ctv[dd] >= (real)0) != second[i];
@@ -394,15 +432,19 @@ __device__ __forceinline__ void swap_rows(float (&a)[NQ], float (&b)[NQ])
 // rows behind of f (fb) and of g (gb), the full row of g just computed (ga),
 // the edge cells (ef, el) and the gathered halo values of stage A's row
 // (hb, hbl).
-template <typename real, bool TAUF, class Diag>
+template <typename real, bool TAUF, bool ROT, class Diag>
 __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int strip, int i0, int i1, bool down,
                                        real (*fb)[64], real (*gb)[64], real (*ga)[64], real (*ef)[FUSE_ROWS][16],
                                        double (*el)[FUSE_ROWS], real *hb, double *hbl, Diag &DA, Diag &DB,
                                        bool diagA, bool diagB)
 {
-    const Strip<real, false> S(dp, bufs, strip);
+    const Strip<real, ROT> S(dp, bufs, strip);
     const int lane = S.lane;
-    const double2 cs = dp->cs[S.pc];
+    double2 cs = dp->cs[S.pc];
+    // a periodic image of a rotated sector (its data turned by S.rot): the
+    // angle turned by the sector, so that its stage-A row, which stage B of
+    // the lanes beside it reads, is in the strip's frame
+    if constexpr (ROT) cs = turn_cs(cs, (8 - S.rot) & 7);
     const real cth = (real)cs.x, sth = (real)cs.y;
     const real crv[4] = {cth, (real)SQH * (cth + sth), sth, (real)SQH * (sth - cth)};
     const real ctv[4] = {-sth, (real)SQH * (cth - sth), cth, (real)SQH * (cth + sth)};
@@ -461,9 +503,9 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
     // float64 keeps two (its 16-row blocks fill the lanes with two; with
     // both forms compiled into its kernel it ran 2 us per launch slower)
     if (sizeof(real) == 4 && i1 - i0 <= 8)
-        edge_cells<real, TAUF, 4>(S, strip, i0, i1, ef, el);
+        edge_cells<real, TAUF, 4, ROT>(S, strip, i0, i1, ef, el);
     else
-        edge_cells<real, TAUF, 2>(S, strip, i0, i1, ef, el);
+        edge_cells<real, TAUF, 2, ROT>(S, strip, i0, i1, ef, el);
     // TAUF: exp(-dt/tau) of stage A's row (oa), loaded a pass ahead, and of
     // stage B's (ob), the row stage A had a pass before (loaded at the point
     // of use, the field cost 7.2 us per float64 launch and 4.2 us per float32
@@ -577,8 +619,9 @@ struct Step2Occ {
 // march), which keeps the parity.  One wavefront per SIMD in float64, where
 // the two steps' rows fill the register file and the LDS rows of four
 // wavefronts most of a CU's LDS; two in float32, whose rows take half the
-// LDS.
-template <typename real, bool TAUF>
+// LDS.  ROT: solves of rotated sectors (no disc), whose periodic images have
+// their directions and angles turned by the sector.
+template <typename real, bool TAUF, bool ROT>
 __global__ __launch_bounds__(BLOCK, Step2Occ<real>::waves) void k_step2(const SolveDesc *descs, const uint2 *tiles,
                                                                        int ntiles, const int64_t *bases,
                                                                        int64_t step_off, const int *flips, int flip,
@@ -615,7 +658,7 @@ __global__ __launch_bounds__(BLOCK, Step2Occ<real>::waves) void k_step2(const So
         // one step, with the row behind in the LDS row of g
         const bool diag = records(dp, step);
         double red[5] = {0, 0, 0, 0, 0};
-        march<real, false, TAUF>(dp, bufs, strip, i0, i1, (rb & 1) != 0, ga[w], red, diag);
+        march<real, ROT, TAUF>(dp, bufs, strip, i0, i1, (rb & 1) != 0, ga[w], red, diag);
         if (diag) {
             const int64_t slot = (step / dp->diag_every) % PART_RING;
             double *part = dp->wpart + ((size_t)slot * dp->nwaves + lt) * 5;
@@ -630,8 +673,8 @@ __global__ __launch_bounds__(BLOCK, Step2Occ<real>::waves) void k_step2(const So
     }
     const bool diagA = records(dp, step), diagB = records(dp, step + 1);
     LaneDiag DA, DB;
-    march2<real, TAUF>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w], DA,
-                       DB, diagA, diagB);
+    march2<real, TAUF, ROT>(dp, bufs, strip, i0, i1, (rb & 1) != 0, fb[w], gb[w], ga[w], ef[w], el[w], hb[w], hbl[w],
+                            DA, DB, diagA, diagB);
     // both steps' totals first (independent DPP chains the compiler can
     // interleave), then one lane stores them
     double v[2][5];
@@ -654,27 +697,25 @@ __global__ __launch_bounds__(BLOCK, Step2Occ<real>::waves) void k_step2(const So
 
 }  // namespace
 
+template <typename real, bool TAUF, bool ROT>
+static void launch_k_step2(int nb, hipStream_t st, const SolveDesc *descs, const uint2 *tiles, int ntiles,
+                           const int64_t *bases, int64_t step_off, const int *flips, int flip, bool single)
+{
+    hipLaunchKernelGGL((k_step2<real, TAUF, ROT>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases, step_off,
+                       flips, flip, (int)single);
+}
+
 hipError_t launch_step2(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases,
-                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, bool tauf,
+                        int64_t step_off, const int *flips, int flip, bool single, bool fp32, bool tauf, bool rot,
                         hipStream_t st)
 {
     const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0) return hipSuccess;
-    if (fp32) {
-        if (tauf)
-            hipLaunchKernelGGL((k_step2<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flips, flip, (int)single);
-        else
-            hipLaunchKernelGGL((k_step2<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flips, flip, (int)single);
-    } else {
-        if (tauf)
-            hipLaunchKernelGGL((k_step2<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flips, flip, (int)single);
-        else
-            hipLaunchKernelGGL((k_step2<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
-                               step_off, flips, flip, (int)single);
-    }
+    auto *fn = fp32 ? (rot ? (tauf ? &launch_k_step2<float, true, true> : &launch_k_step2<float, false, true>)
+                           : (tauf ? &launch_k_step2<float, true, false> : &launch_k_step2<float, false, false>))
+                    : (rot ? (tauf ? &launch_k_step2<double, true, true> : &launch_k_step2<double, false, true>)
+                           : (tauf ? &launch_k_step2<double, true, false> : &launch_k_step2<double, false, false>));
+    fn(nb, st, descs, tiles, ntiles, bases, step_off, flips, flip, single);
     return hipGetLastError();
 }
 

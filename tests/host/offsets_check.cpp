@@ -137,11 +137,18 @@ void check_grid(const Grid &g)
                 access(g, "tau field", (uint64_t)row * b.rest, (uint32_t)row * b.rest, o.vo, es, OM, strip, lane);
             }
         }
-    if (rotated) return;  // the two-step kernel takes full annuli only
+    // the two-step kernel's edge cells (rotated sectors: the pair of each
+    // column's turned directions, one of the 16 checked here)
     for (int strip = 0; strip < nstrip; ++strip)
         for (int side = 0; side < 2; ++side)
             for (int r = 0; r < g.nr; ++r) {
-                const EdgeOffsets o = edge_offsets(g.nr, g.nt, g.esz, b, strip, side, r);
+                const EdgeOffsets o = edge_offsets(g.nr, g.nt, g.sector, rotated, g.esz, b, strip, side, r);
+                for (int t : {o.tc, o.tl, o.tr, o.tk})
+                    if ((t < 0 || t > 7) && n_failed++ < 20)
+                        std::fprintf(stderr, "edge direction shift %d: strip %d row %d\n", t, strip, r);
+                for (int pcol : {o.pc, o.pl, o.pr, o.pk})
+                    if ((pcol < 0 || pcol >= g.nt) && n_failed++ < 20)
+                        std::fprintf(stderr, "edge column %d outside the grid: strip %d row %d\n", pcol, strip, r);
                 access(g, "edge rest", 0, 0, o.x0, es, F, strip, r);
                 for (int i = 0; i < 16; ++i) {
                     const uint32_t po = pair_in_row(b, i);

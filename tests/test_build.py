@@ -150,9 +150,8 @@ def test_step_kernel_takes_lane_shifts_with_every_lane_active():
     exec-narrowing instruction and the matching restore."""
     asm = _step_kernels_asm()
     bodies = list(_kernel_bodies(asm, "k_step"))
-    # k_step: 2 precisions x (full annulus, rotated sector) x (tau of the solve, per-cell tau); k_step2: 2
-    # precisions x the two kinds of tau
-    assert len(bodies) == 12
+    # k_step and k_step2: 2 precisions x (full annulus, rotated sector) x (tau of the solve, per-cell tau)
+    assert len(bodies) == 16
     for name, lines in bodies:
         shifts = sum(("wave_shr:1" in t or "wave_shl:1" in t) for t in lines)
         dpp = sum(bool(re.search(r"\b(wave_sh[lr]|row_|quad_perm)", t)) for t in lines)
@@ -195,4 +194,4 @@ def test_step_kernel_uses_no_scratch_memory():
             continue
         seen += 1
         assert int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1)) == 0, name
-    assert seen == 16
+    assert seen == 20

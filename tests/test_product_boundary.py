@@ -80,4 +80,4 @@ def test_bench_line_contract():
     side = d["side_kernels"]
     assert side["noneq"]["avg_us"] > 0 and 0 < side["noneq"]["frac_of_peak"] < 1
     assert side["tau_field"]["avg_launch_us"] > 0 and side["tau_field"]["plain_avg_launch_us"] > 0
-    assert side["sector"]["avg_launch_us"] > 0 and 0 < side["sector"]["frac_of_peak"] < 1
+    assert side["sector"]["avg_launch_us"] > 0 and 0 < side["sector"]["effective_frac_of_peak"] < 1

@@ -99,3 +99,48 @@ def test_strip_groups_of_whole_workgroups(nt, precision):
         err = np.array([np.abs(F[k] - R[k]).max() / sc[k] for k in range(6)])
         print(f"nt={nt} nr={nr} steps={nsteps} precision={precision}: max err {err.max():.2e}", flush=True)
         assert np.isfinite(err).all() and err.max() < tol, (nr, nt, err)
+
+
+@pytest.mark.parametrize("sector", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_rotated_sectors_in_pairs(sector, precision):
+    """Annular sectors step two steps per launch: the periodic images past
+    the last column, and the edge cells at the sector's ends, carry the
+    directions and the angles turned by the sector.  Widths leave none, one
+    or most lanes of the last strip to images (of several turns where the
+    sector is narrow), row counts give blocks of one or two rows, and odd
+    step counts end with a one-step launch.  Against the oracle: float64 at
+    the parity bound, float32 at its own."""
+    tol = TOL64 if precision == P.PDBM_FP64 else 1e-4
+    for nr, nt, nsteps in ((1, 17, 12), (5, 63, 13), (33, 65, 12), (12, 130, 9)):
+        w = replace(_case(nr, nt, sector=sector), nsteps=nsteps)
+        s = P.Solver(P.make_params(**w.params_kw(), precision=precision), P.make_ic(**w.ic_kw()))
+        s.step(w.nsteps)
+        F, _ = s.moments(check=False)
+        o = O.Solver(O.make_params(**w.params_kw()))
+        o.init_ic(**w.ic_kw())
+        o.step(w.nsteps)
+        R = o.fields()
+        sc = _scales(R)
+        err = np.array([np.abs(F[k] - R[k]).max() / sc[k] for k in range(6)])
+        print(f"sector={sector} nr={nr} nt={nt} steps={nsteps} precision={precision}: max err {err.max():.2e}",
+              flush=True)
+        assert np.isfinite(err).all() and err.max() < tol, (sector, nr, nt, err)
+
+
+@pytest.mark.parametrize("sector", [1, 3, 4])
+def test_rotated_sector_pairs_equal_single_steps(sector):
+    """A rotated sector stepped two steps per launch equals the same steps
+    taken one launch at a time (step(1) calls take the one-step kernel), to
+    rounding."""
+    w = _case(33, 65, sector=sector)
+    a = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64), P.make_ic(**w.ic_kw()))
+    b = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64), P.make_ic(**w.ic_kw()))
+    for _ in range(10):
+        a.step(1)
+    b.step(10)
+    Fa, _ = a.moments(check=False)
+    Fb, _ = b.moments(check=False)
+    sc = _scales(Fa)
+    err = np.array([np.abs(Fa[k] - Fb[k]).max() / sc[k] for k in range(6)])
+    assert err.max() < 1e-13, (sector, err)
