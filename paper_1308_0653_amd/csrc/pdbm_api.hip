@@ -363,7 +363,7 @@ bool Solve::fusable(bool alone) const
         const char *e = std::getenv("PDBM_FUSE");
         return e && e[0] == '0';
     }();
-    return !off && (alone ? !hd.disc : !rot()) && p.ntheta > 1 && L.rows <= FUSE_ROWS;
+    return !off && (alone || !rot()) && p.ntheta > 1 && L.rows <= FUSE_ROWS;
 }
 
 int Solve::reduce_records(hipStream_t st)

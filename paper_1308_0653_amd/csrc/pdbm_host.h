@@ -76,9 +76,8 @@ class Solve {
     int cur() const { return (int)((step + flip) & 1); }
     // Whether two steps may go in one launch: ntheta > 1, row blocks of at
     // most FUSE_ROWS rows (either precision; PDBM_FUSE=0 turns it off), and
-    // a solve stepped on its own (`alone`) that is no disc, or a member of a
-    // pack on the full annulus (packs launch the variant without rotated
-    // sectors).
+    // a solve stepped on its own (`alone`), or a member of a pack on the full
+    // annulus (packs launch the variant without rotated sectors).
     bool fusable(bool alone = false) const;
     int waves() const { return L.nwaves; }
     bool rot() const { return p.sector != 8; }

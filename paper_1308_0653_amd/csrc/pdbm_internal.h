@@ -95,8 +95,8 @@ hipError_t launch_column(const SolveDesc *desc, int nwaves, int64_t step0, int f
 // step_off, flips and flip as launch_step): reads buffer (s + flip_i) & 1 and
 // writes the other one, so the caller toggles flip_i.  A solve with one step
 // left, or every solve with `single`, takes one step and keeps its parity.
-// ntheta > 1, rows per wavefront at most FUSE_ROWS, no disc; `rot` selects
-// the variant for sectors other than the full annulus.  Makes the drift
+// ntheta > 1, rows per wavefront at most FUSE_ROWS; `rot` selects the
+// variant for sectors other than the full annulus (discs included).  Makes the drift
 // records of the steps it takes as launch_step does; `tauf` as launch_step.
 hipError_t launch_step2(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases,
                         int64_t step_off, const int *flips, int flip, bool single, bool fp32, bool tauf, bool rot,

@@ -1,7 +1,7 @@
 // Two time steps per launch, in one pass over f (k_step2): solves with more
 // than one theta column, full annuli (single or packed) and single rotated
-// sectors that are no disc, in float64 (one wavefront per SIMD) and float32
-// (two).
+// sectors (annuli and discs), in float64 (one wavefront per SIMD) and
+// float32 (two).
 #include "pdbm_device.h"
 
 namespace pdbm {
@@ -235,9 +235,9 @@ __device__ __forceinline__ void edge_cells(const Strip<real, ROT> &S, int strip,
     const int nr = dp->nr, nt = dp->nt;
     const int r = i0 + min(e, count - 1);  // lanes past the block repeat its last row
     const RowBytes rb{S.row_bytes, S.lrow_bytes, S.rest_bytes, S.pair_bytes};
-    // the cell, its radial neighbours (below row 0 the copy of row 0, above
-    // row nr - 1 the copy of row nr - 1: zero-gradient ghosts; the two-step
-    // kernel takes no disc) and its azimuthal neighbours
+    // the cell, its radial neighbours (below row 0 the copy of row 0, or at
+    // a disc centre row 0 with its directions turned by 4; above row nr - 1
+    // the copy of row nr - 1) and its azimuthal neighbours
     const EdgeOffsets o = edge_offsets(nr, nt, dp->sector, ROT, (int)sizeof(real), rb, strip, side, r);
     double2 cs = dp->cs[o.pc], ck = dp->cs[o.pk];
     if constexpr (ROT) {
@@ -280,9 +280,13 @@ __device__ __forceinline__ void edge_cells(const Strip<real, ROT> &S, int strip,
             bload2(a, b, S.fin, o.orow + o.cc + pc, 0u);
             x[i] = sc ? b : a;
             x[i + NP] = sc ? a : b;
+            // the radial neighbour's member: below row 0 of a disc the
+            // ghost is row 0 with every direction turned by 4
             const bool mc = second[i] != sc, mlr = left ? second[i] != sl : second[i] != sr;
+            const bool mlo = mc != (dp->disc && r == 0);
             if constexpr (sizeof(real) == 4) {
-                bload(nbr[i], S.fin, (low ? o.olo : o.ohi) + o.cc + pc + (mc ? (uint32_t)sizeof(real) : 0u), 0u);
+                bload(nbr[i], S.fin, (low ? o.olo : o.ohi) + o.cc + pc + ((low ? mlo : mc) ? (uint32_t)sizeof(real) : 0u),
+                      0u);
                 bload(nbt[i], S.fin, o.orow + (left ? o.cl + pl : o.cr + pr) + (mlr ? (uint32_t)sizeof(real) : 0u),
                       0u);
             } else {
@@ -291,7 +295,7 @@ __device__ __forceinline__ void edge_cells(const Strip<real, ROT> &S, int strip,
                 bload2(hi0, hi1, S.fin, o.ohi + o.cc + pc, 0u);
                 bload2(l0, l1, S.fin, o.orow + o.cl + pl, 0u);
                 bload2(r0, r1, S.fin, o.orow + o.cr + pr, 0u);
-                nbr[i] = mc ? (low ? lo1 : hi1) : (low ? lo0 : hi0);
+                nbr[i] = low ? (mlo ? lo1 : lo0) : (mc ? hi1 : hi0);
                 nbt[i] = left ? (mlr ? l1 : l0) : (mlr ? r1 : r0);
             }
             continue;
@@ -545,9 +549,17 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
             stage_row<real, true, TAUF>(S, ir, fb, fc, fn, ga, gc, H, lp, lc, ln, mr, mt, acr, ctv, !down, cs.x, cs.y,
                                         gln, oa, DA, diagA && p >= 0 && p < count);
         } else {
-            // beyond the last grid row: the zero-gradient ghost of g
+            // beyond the last grid row: the zero-gradient ghost of g (at a
+            // disc centre, row 0 with every direction turned by 4)
+            if constexpr (ROT) {
+                const bool turn = dp->disc && rafter < 0;
+                gc[0] = ga[0][lane];
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) gc[q] = ga[q][lane];
+                for (int q = 1; q < NQ; ++q) gc[q] = ga[turn ? (((q - 1) ^ 4) + 1) : q][lane];
+            } else {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) gc[q] = ga[q][lane];
+            }
             gln = glc;
         }
         // f at position p + 2 (the row ahead of the next stage A) replaces f(p)
@@ -562,12 +574,22 @@ __device__ __forceinline__ void march2(DescPtr dp, const StepBufs &bufs, int str
         // (B) second step at position p - 1
         if (p == 0 && !vlo) {
             // the row behind stage B's first row is the (zero-gradient)
-            // ghost of g(0)
+            // ghost of g(0) (at a disc centre with every direction turned by
+            // 4: the slot of direction dd takes g(0)'s direction dd + 4)
+            if constexpr (ROT) {
+                const bool turn = dp->disc && rbefore < 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
+                for (int k = 0; k < 4; ++k)
 #pragma unroll
-                for (int dd = 0; dd < 4; ++dd)
-                    gb[4 * k + dd][lane] = mr[dd] ? ga[1 + 8 * k + dd][lane] : ga[5 + 8 * k + dd][lane];
+                    for (int dd = 0; dd < 4; ++dd)
+                        gb[4 * k + dd][lane] = mr[dd] != turn ? ga[1 + 8 * k + dd][lane] : ga[5 + 8 * k + dd][lane];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int dd = 0; dd < 4; ++dd)
+                        gb[4 * k + dd][lane] = mr[dd] ? ga[1 + 8 * k + dd][lane] : ga[5 + 8 * k + dd][lane];
+            }
             glc = gln;
         } else if (p > 0) {
             const int e = ir - step - i0;
@@ -619,8 +641,8 @@ struct Step2Occ {
 // march), which keeps the parity.  One wavefront per SIMD in float64, where
 // the two steps' rows fill the register file and the LDS rows of four
 // wavefronts most of a CU's LDS; two in float32, whose rows take half the
-// LDS.  ROT: solves of rotated sectors (no disc), whose periodic images have
-// their directions and angles turned by the sector.
+// LDS.  ROT: solves of rotated sectors, discs included, whose periodic
+// images have their directions and angles turned by the sector.
 template <typename real, bool TAUF, bool ROT>
 __global__ __launch_bounds__(BLOCK, Step2Occ<real>::waves) void k_step2(const SolveDesc *descs, const uint2 *tiles,
                                                                        int ntiles, const int64_t *bases,

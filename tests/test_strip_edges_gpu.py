@@ -21,9 +21,9 @@ TOL64 = 1e-10
 WIDTHS = [1, 2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 200]
 
 
-def _case(nr, nt, sector=8, seed=0):
+def _case(nr, nt, sector=8, seed=0, r_min=0.3):
     # a reacting, moving, noisy state: ignition inside r < 0.55
-    return replace(W.small_fp64(), nr=nr, ntheta=nt, r_min=0.3, r_max=1.0, dt=2e-5, tau=5e-5, r_split=0.55,
+    return replace(W.small_fp64(), nr=nr, ntheta=nt, r_min=r_min, r_max=1.0, dt=2e-5, tau=5e-5, r_split=0.55,
                    sector=sector, p_noise=1e-3, seed=seed, nsteps=12)
 
 
@@ -128,12 +128,37 @@ def test_rotated_sectors_in_pairs(sector, precision):
         assert np.isfinite(err).all() and err.max() < tol, (sector, nr, nt, err)
 
 
+@pytest.mark.parametrize("sector", [1, 2, 4])
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_rotated_discs_in_pairs(sector, precision):
+    """Discs of the sectors with the disc-centre rule (Sec. II.D) step two
+    steps per launch too: below row 0 the ghost is row 0 with every
+    direction turned by 4, for stage A's rows, for stage B's row behind the
+    first block and for the edge cells' radial neighbours.  Against the
+    oracle, as above."""
+    tol = TOL64 if precision == P.PDBM_FP64 else 1e-4
+    for nr, nt, nsteps in ((1, 17, 12), (5, 65, 13), (33, 17, 12), (12, 130, 9)):
+        w = replace(_case(nr, nt, sector=sector, r_min=0.0), nsteps=nsteps)
+        s = P.Solver(P.make_params(**w.params_kw(), precision=precision), P.make_ic(**w.ic_kw()))
+        s.step(w.nsteps)
+        F, _ = s.moments(check=False)
+        o = O.Solver(O.make_params(**w.params_kw()))
+        o.init_ic(**w.ic_kw())
+        o.step(w.nsteps)
+        R = o.fields()
+        sc = _scales(R)
+        err = np.array([np.abs(F[k] - R[k]).max() / sc[k] for k in range(6)])
+        print(f"disc sector={sector} nr={nr} nt={nt} steps={nsteps} precision={precision}: max err {err.max():.2e}",
+              flush=True)
+        assert np.isfinite(err).all() and err.max() < tol, (sector, nr, nt, err)
+
+
 @pytest.mark.parametrize("sector", [1, 3, 4])
 def test_rotated_sector_pairs_equal_single_steps(sector):
-    """A rotated sector stepped two steps per launch equals the same steps
-    taken one launch at a time (step(1) calls take the one-step kernel), to
-    rounding."""
-    w = _case(33, 65, sector=sector)
+    """A rotated sector (the half one as a disc) stepped two steps per launch
+    equals the same steps taken one launch at a time (step(1) calls take the
+    one-step kernel), to rounding."""
+    w = _case(33, 65, sector=sector, r_min=0.0 if sector == 4 else 0.3)  # the half disc with its centre rule
     a = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64), P.make_ic(**w.ic_kw()))
     b = P.Solver(P.make_params(**w.params_kw(), precision=P.PDBM_FP64), P.make_ic(**w.ic_kw()))
     for _ in range(10):
