@@ -357,13 +357,13 @@ int Solve::set_step(int64_t s, hipStream_t st)
     return PDBM_OK;
 }
 
-bool Solve::fusable(bool alone) const
+bool Solve::fusable() const
 {
     static const bool off = [] {
         const char *e = std::getenv("PDBM_FUSE");
         return e && e[0] == '0';
     }();
-    return !off && (alone || !rot()) && p.ntheta > 1 && L.rows <= FUSE_ROWS;
+    return !off && p.ntheta > 1 && L.rows <= FUSE_ROWS;
 }
 
 int Solve::reduce_records(hipStream_t st)
@@ -480,7 +480,7 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
 {
     if (!h || nsteps < 0) return fail(PDBM_EINVAL, "bad solver or step count");
     Solve &s = h->s;
-    const bool pairs = s.fusable(true);
+    const bool pairs = s.fusable();
     const bool column = s.p.ntheta == 1;
     const int most = column ? COL_K : 2;  // steps of one launch, at most
     for (int64_t i = 0; i < nsteps;) {

@@ -74,11 +74,10 @@ class Solve {
     void release();  // frees an owned workspace (the stream must be idle)
 
     int cur() const { return (int)((step + flip) & 1); }
-    // Whether two steps may go in one launch: ntheta > 1, row blocks of at
-    // most FUSE_ROWS rows (either precision; PDBM_FUSE=0 turns it off), and
-    // a solve stepped on its own (`alone`), or a member of a pack on the full
-    // annulus (packs launch the variant without rotated sectors).
-    bool fusable(bool alone = false) const;
+    // Whether two steps may go in one launch: ntheta > 1 and row blocks of
+    // at most FUSE_ROWS rows (either precision, any sector; PDBM_FUSE=0
+    // turns it off).
+    bool fusable() const;
     int waves() const { return L.nwaves; }
     bool rot() const { return p.sector != 8; }
     bool tauf() const { return hd.omegaf != nullptr; }  // relaxes with a per-cell tau

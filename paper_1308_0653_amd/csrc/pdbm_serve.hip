@@ -45,7 +45,8 @@ class Pack {
 
     // Uploads the description, step-base, buffer-parity and tile tables of
     // the current members and drops the captured graph.  The pack steps in
-    // pairs when every member may (Solve::fusable).  Synchronises st.
+    // pairs when every member may (Solve::fusable), with the variant for
+    // rotated sectors when a member is one.  Synchronises st.
     int rebuild(hipStream_t st)
     {
         drop_graph();
@@ -179,9 +180,9 @@ class Pack {
         hipError_t e = hipSuccess;
         if (pairs) {
             for (int i = 0; 2 * i + 1 < n && e == hipSuccess; ++i)
-                e = launch_step2(ddescs, dtiles, ntiles, dbases, 2 * i, dflips, i & 1, false, fp32, false, false, st);
+                e = launch_step2(ddescs, dtiles, ntiles, dbases, 2 * i, dflips, i & 1, false, fp32, false, rot, st);
             if (e == hipSuccess && (n & 1))
-                e = launch_step2(ddescs, dtiles, ntiles, dbases, n - 1, dflips, (n / 2) & 1, true, fp32, false, false, st);
+                e = launch_step2(ddescs, dtiles, ntiles, dbases, n - 1, dflips, (n / 2) & 1, true, fp32, false, rot, st);
         } else {
             for (int i = 0; i < n && e == hipSuccess; ++i)
                 e = launch_step(ddescs, dtiles, ntiles, dbases, i, dflips, 0, fp32, rot, false, st);
@@ -212,8 +213,8 @@ class Pack {
 };
 
 // Rows per wavefront of a packed solve: FUSE_ROWS for one that can step in
-// pairs (full annulus, ntheta > 1), ONE_STEP_BATCH_ROWS otherwise;
-// PDBM_BATCH_ROWS overrides both (tuning).
+// pairs (ntheta > 1), ONE_STEP_BATCH_ROWS otherwise; PDBM_BATCH_ROWS
+// overrides both (tuning).
 int batch_rows(const pdbm_params &p)
 {
     static const int env = [] {
@@ -221,7 +222,7 @@ int batch_rows(const pdbm_params &p)
         return e ? std::atoi(e) : 0;
     }();
     if (env > 0) return env;
-    return p.ntheta > 1 && p.sector == 8 ? FUSE_ROWS : ONE_STEP_BATCH_ROWS;
+    return p.ntheta > 1 ? FUSE_ROWS : ONE_STEP_BATCH_ROWS;
 }
 
 // Fields [6][nr][ntheta] (host, may be NULL) and drift report of a member.

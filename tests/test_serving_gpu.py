@@ -358,14 +358,14 @@ def test_packed_pairs_with_odd_counts(precision):
 
 @pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
 def test_pack_switches_between_pairs_and_single_steps(precision):
-    """Rotated-sector solves, which cannot step in pairs, join a pack whose
-    members have been stepping in pairs: the pack then takes one step per
-    launch, reading each member's state from the buffer its pairs left it in
-    (chunks of 6 steps are 3 pairs, so that parity changes with every chunk),
-    and returns to pairs when they leave.  Every result agrees with its solo
-    solve to rounding and with the oracle."""
+    """Single-column solves, which packs step one step per launch, join a
+    pack whose members have been stepping in pairs: the pack then takes one
+    step per launch, reading each member's state from the buffer its pairs
+    left it in (chunks of 6 steps are 3 pairs, so that parity changes with
+    every chunk), and returns to pairs when they leave.  Every result agrees
+    with its solo solve to rounding and with the oracle."""
     ws = _small_sweep(2, seed=12)
-    sec = replace(W.small_fp64(), nr=24, ntheta=24, sector=3, r_min=0.5, dt=1e-4, tau=4e-4, r_split=0.7)
+    sec = replace(W.small_fp64(), name="column", nr=40, ntheta=1, r_min=0.5, dt=1e-4, tau=4e-4, r_split=0.7)
     srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=4, chunk_steps=6)
     n_long, n_sec = 601, 31
     long_ids = [srv.submit(_params(w, precision), P.make_ic(**w.ic_kw()), n_long, keep_fields=True) for w in ws]
@@ -377,7 +377,7 @@ def test_pack_switches_between_pairs_and_single_steps(precision):
             time.sleep(0.0005)
         sec_ids.append(srv.submit(_params(sec, precision), P.make_ic(**sec.ic_kw()), n_sec, keep_fields=True))
     assert srv.wait(120.0)
-    for sid in sec_ids:  # the sector solves ran while the long ones did
+    for sid in sec_ids:  # the single-column solves ran while the long ones did
         assert max(srv.times(i)[1] for i in long_ids) < srv.times(sid)[1] < min(srv.times(i)[2] for i in long_ids)
     tol = 1e-12 if precision == P.PDBM_FP64 else 1e-4
     otol = 1e-10 if precision == P.PDBM_FP64 else 1e-4
@@ -385,6 +385,39 @@ def test_pack_switches_between_pairs_and_single_steps(precision):
         state, F, _ = srv.poll(rid, fields=True)
         assert state == P.PDBM_DONE
         solo = P.Solver(_params(w, precision), P.make_ic(**w.ic_kw()))
+        solo.step(n)
+        errs = _field_errs(F, solo.moments()[0])
+        print(f"{w.name} n={n} prec={precision}: max rel {max(errs):.2e}", flush=True)
+        assert max(errs) <= tol, (w.name, errs)
+        errs = _field_errs(F, _oracle_fields(w, n))
+        assert max(errs[k] for k in (0, 3, 5)) <= otol, (w.name, errs)
+    srv.close()
+
+
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_packs_with_rotated_sectors_step_in_pairs(precision):
+    """A pack holding rotated sectors, an annular one and a half disc with
+    its centre rule, beside full annuli, still steps in pairs (the rotated
+    variant of the two-step kernel takes every member).  Odd counts in
+    chunks of 7; every result agrees with its solo solve to rounding and
+    with the oracle."""
+    ws = _small_sweep(2, seed=13)
+    ws.append(replace(W.small_fp64(), name="sector3", nr=24, ntheta=24, sector=3, r_min=0.5, dt=1e-4, tau=4e-4,
+                      r_split=0.7))
+    ws.append(W.Workload("halfdisc", 40, 8, 0.0, 1.0, dt=2e-4, tau=2e-4, w1=1.0, w2=50.0, m=1, n=1, Q=1.0,
+                         T_th=1.1, r_split=0.3, inner=(1.5, 1.55556, 0.666667, 0.0, 1.0),
+                         outer=(1.0, 1.0, 0.0, 0.0, 0.0), p_noise=1e-6, seed=3, nsteps=40, sector=4))
+    counts = [33, 26, 29, 40]
+    srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=4, chunk_steps=7)
+    ids = [srv.submit(_params(w, precision, diag_every=5), P.make_ic(**w.ic_kw()), n, keep_fields=True)
+           for w, n in zip(ws, counts)]
+    assert srv.wait(60.0)
+    tol = 1e-12 if precision == P.PDBM_FP64 else 1e-5
+    otol = 1e-10 if precision == P.PDBM_FP64 else 1e-4
+    for rid, w, n in zip(ids, ws, counts):
+        state, F, _ = srv.poll(rid, fields=True)
+        assert state == P.PDBM_DONE
+        solo = P.Solver(_params(w, precision, diag_every=5), P.make_ic(**w.ic_kw()))
         solo.step(n)
         errs = _field_errs(F, solo.moments()[0])
         print(f"{w.name} n={n} prec={precision}: max rel {max(errs):.2e}", flush=True)
