@@ -1,7 +1,6 @@
 // Two time steps per launch, in one pass over f (k_step2): solves with more
-// than one theta column, full annuli (single or packed) and single rotated
-// sectors (annuli and discs), in float64 (one wavefront per SIMD) and
-// float32 (two).
+// than one theta column, full annuli and rotated sectors (annuli and discs),
+// single or packed, in float64 (one wavefront per SIMD) and float32 (two).
 #include "pdbm_device.h"
 
 namespace pdbm {
