@@ -296,8 +296,9 @@ enum { PDBM_MAX_CHUNK = 64 }; /* most steps captured in one graph */
 
 /* A fixed set of independent solves (each with its own grid, parameters and
  * initial state; all of one precision) advanced together: one launch takes
- * every member two steps (one step where a count is odd, and one per launch
- * in packs holding a single theta column), and runs of
+ * every member two steps (one step where a count is odd; up to 8 steps in
+ * packs of single theta columns only, and one per launch in packs that mix
+ * single columns with wider grids), and runs of
  * `chunk_steps` steps are captured once in a HIP graph and replayed (chunk_steps = 0: plain
  * launches; at most PDBM_MAX_CHUNK, else PDBM_EINVAL).  Graphs need a stream other than the null stream: with
  * stream = NULL and chunk_steps > 1 the batch creates a stream of its own.

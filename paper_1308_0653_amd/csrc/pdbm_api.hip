@@ -488,7 +488,8 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
             // a single column: up to COL_K steps per launch; the state moves
             // to the other buffer, which toggles the parity unless nk is odd
             const int nk = (int)std::min<int64_t>(COL_K, nsteps - i);
-            HIPCHK(launch_column(s.dd, s.waves(), s.step, s.flip, nk, s.fp32, s.tauf(), h->st));
+            HIPCHK(launch_column(s.dd, nullptr, s.waves(), nullptr, s.step, nullptr, s.flip, nk, s.fp32, s.tauf(),
+                                 h->st));
             s.step += nk;
             s.flip ^= (nk + 1) & 1;
             i += nk;

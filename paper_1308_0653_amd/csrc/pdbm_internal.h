@@ -86,11 +86,12 @@ struct DiagCtl {
 // left.
 hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases, int64_t step_off,
                        const int *flips, int flip, bool fp32, bool rot, bool tauf, hipStream_t st);
-// Up to COL_K steps (nk) of a single-column single solve (ntheta = 1) in one
-// launch of k_column; the state of step0 is in buffer (step0 + flip) & 1 and
-// the new one goes to the other buffer.
-hipError_t launch_column(const SolveDesc *desc, int nwaves, int64_t step0, int flip, int nk, bool fp32, bool tauf,
-                         hipStream_t st);
+// Up to COL_K steps (nk) of single-column solves (ntheta = 1) in one launch
+// of k_column; tiles, bases, step_off, flips and flip as launch_step.  Solve
+// i takes min(nk, steps it has left) steps from buffer (s + flip_i) & 1 into
+// the other one, so the caller toggles flip_i when that count is even.
+hipError_t launch_column(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases,
+                         int64_t step_off, const int *flips, int flip, int nk, bool fp32, bool tauf, hipStream_t st);
 // Steps s and s + 1 of every solve of the launch in one pass (tiles, bases,
 // step_off, flips and flip as launch_step): reads buffer (s + flip_i) & 1 and
 // writes the other one, so the caller toggles flip_i.  A solve with one step
@@ -111,8 +112,12 @@ hipError_t launch_noneq(const SolveDesc &d, int cur, bool fp32, double *out, hip
 // bases[i] += by for i < n.  With flips (after `by` steps taken as two-step
 // launches, a single launch closing an odd count): flips[i] toggles when
 // solve i took an odd number of two-step launches, min(left, by) / 2 of them
-// with left = max(nsteps - bases[i], 0).
-hipError_t launch_advance(const SolveDesc *descs, int *flips, int64_t *bases, int n, int64_t by, hipStream_t st);
+// with left = max(nsteps - bases[i], 0).  With flips and column_k > 0 (the
+// steps taken as k_column launches of min(column_k, steps of the run left)):
+// flips[i] toggles for each launch in which solve i took an even number of
+// steps.
+hipError_t launch_advance(const SolveDesc *descs, int *flips, int64_t *bases, int n, int64_t by, int column_k,
+                          hipStream_t st);
 // Drift records of steps [base + lo, base + hi) of solves descs[0..n), base =
 // bases[i] (0 if bases is NULL); at most PART_RING steps per call, and the
 // steps must have been launched before on the same stream.

@@ -46,12 +46,14 @@ class Pack {
     // Uploads the description, step-base, buffer-parity and tile tables of
     // the current members and drops the captured graph.  The pack steps in
     // pairs when every member may (Solve::fusable), with the variant for
-    // rotated sectors when a member is one.  Synchronises st.
+    // rotated sectors when a member is one, and up to COL_K steps per launch
+    // when every member is a single column.  Synchronises st.
     int rebuild(hipStream_t st)
     {
         drop_graph();
         rot = false;
         pairs = !members.empty();
+        columns = !members.empty();
         std::vector<SolveDesc> descs;
         std::vector<uint2> tiles;
         bases_host.clear();
@@ -62,6 +64,7 @@ class Pack {
             flips_host.push_back(members[i]->flip);
             rot = rot || members[i]->rot();
             pairs = pairs && members[i]->fusable();
+            columns = columns && members[i]->p.ntheta == 1;
             for (int t = 0; t < members[i]->waves(); ++t) tiles.push_back(make_uint2((unsigned)i, (unsigned)t));
         }
         ntiles = (int)tiles.size();
@@ -131,6 +134,7 @@ class Pack {
     int64_t *dbases = nullptr;  // step of each member at the start of the next chunk
     int *dflips = nullptr;      // buffer parity of each member (Solve::flip) at that step
     bool pairs = false;         // two steps per launch
+    bool columns = false;       // single columns only: up to COL_K steps per launch (k_column)
     std::vector<int64_t> bases_host;
     std::vector<int> flips_host;
     size_t cap_descs = 0, cap_tiles = 0, cap_bases = 0, cap_flips = 0;
@@ -170,15 +174,25 @@ class Pack {
     }
 
     // n <= PART_RING steps of every member, their drift records, and the
-    // advance of the step bases (and, in pairs, of the buffer parities).  In
-    // pairs, two-step launch i takes steps 2i and 2i + 1 with parity flips ^
-    // (i & 1) (every member still running has taken the i launches before),
-    // and an odd n ends with a launch of single steps.
+    // advance of the step bases (and, in pairs or columns, of the buffer
+    // parities).  In pairs, two-step launch i takes steps 2i and 2i + 1 with
+    // parity flips ^ (i & 1) (every member still running has taken the i
+    // launches before), and an odd n ends with a launch of single steps.  In
+    // columns, launches of nk = min(COL_K, steps of the chunk left) steps;
+    // each toggles the parity of the members still running when nk is even.
     hipError_t enqueue_steps(int n, hipStream_t st)
     {
         const int nm = (int)members.size();
         hipError_t e = hipSuccess;
-        if (pairs) {
+        if (columns) {
+            int pf = 0;
+            for (int done = 0; done < n && e == hipSuccess;) {
+                const int nk = std::min(COL_K, n - done);
+                e = launch_column(ddescs, dtiles, ntiles, dbases, done, dflips, pf, nk, fp32, false, st);
+                pf ^= (nk + 1) & 1;
+                done += nk;
+            }
+        } else if (pairs) {
             for (int i = 0; 2 * i + 1 < n && e == hipSuccess; ++i)
                 e = launch_step2(ddescs, dtiles, ntiles, dbases, 2 * i, dflips, i & 1, false, fp32, false, rot, st);
             if (e == hipSuccess && (n & 1))
@@ -188,7 +202,8 @@ class Pack {
                 e = launch_step(ddescs, dtiles, ntiles, dbases, i, dflips, 0, fp32, rot, false, st);
         }
         if (e == hipSuccess) e = launch_records(ddescs, nm, dbases, 0, n, st);
-        if (e == hipSuccess) e = launch_advance(ddescs, pairs ? dflips : nullptr, dbases, nm, n, st);
+        if (e == hipSuccess)
+            e = launch_advance(ddescs, pairs || columns ? dflips : nullptr, dbases, nm, n, columns ? COL_K : 0, st);
         return e;
     }
 
@@ -197,7 +212,19 @@ class Pack {
     {
         for (Solve *m : members) {
             const int64_t left = std::max<int64_t>(m->hd.nsteps - m->step, 0);
-            if (pairs) m->flip ^= (int)((std::min(left, n) / 2) & 1);
+            if (columns) {
+                // as k_advance: the launches of the chunk, min(COL_K, steps of it left) steps each
+                int64_t l = left;
+                for (int64_t done = 0; done < n && l > 0;) {
+                    const int64_t run = std::min<int64_t>(COL_K, n - done);
+                    const int64_t nk = std::min(run, l);
+                    m->flip ^= (int)((nk + 1) & 1);
+                    l -= nk;
+                    done += run;
+                }
+            } else if (pairs) {
+                m->flip ^= (int)((std::min(left, n) / 2) & 1);
+            }
             m->step = std::min(m->step + n, m->hd.nsteps);
         }
     }

@@ -146,18 +146,32 @@ __device__ __forceinline__ void radial_block(DescPtr dp, const StepBufs &bufs, i
 // cell itself with directions turned by the sector, as in radial_block, and
 // the arithmetic per cell is the same.  Drift partial sums of each recorded
 // step come from the owned lanes' state at the start of that step.
+// Packed launches as k_step's (tiles, bases, step_off, flips, flip): solve i
+// takes steps bases[i] + step_off on, min(nk, its steps left) of them, from
+// buffer (step + flip_i) & 1 into the other one.
 template <typename real, bool TAUF>
-__global__ __launch_bounds__(BLOCK, 1) void k_column(const SolveDesc *desc, int64_t step0, int flip, int nk)
+__global__ __launch_bounds__(BLOCK, 1) void k_column(const SolveDesc *descs, const uint2 *tiles, int ntiles,
+                                                     const int64_t *bases, int64_t step_off, const int *flips,
+                                                     int flip, int nk_most)
 {
-    const DescPtr dp = (DescPtr)desc;
     const int nb = gridDim.x;
-    const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, nb) * (BLOCK / 64) + (threadIdx.x >> 6));
-    if (t >= dp->nwaves) return;
+    const int tg = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, nb) * (BLOCK / 64) + (threadIdx.x >> 6));
+    if (tg >= ntiles) return;
+    int solve = 0, t = tg;
+    if (tiles) {
+        const uint2 e = tiles[tg];
+        solve = __builtin_amdgcn_readfirstlane((int)e.x);
+        t = __builtin_amdgcn_readfirstlane((int)e.y);
+    }
+    const DescPtr dp = (DescPtr)(descs + solve);
+    const int64_t step0 = (bases ? bases[solve] : 0) + step_off;
+    if (step0 >= dp->nsteps) return;
+    const int nk = (int)min((int64_t)nk_most, dp->nsteps - step0);
     __shared__ real slots[BLOCK / 64][NQ][64];
     real(*slot)[64] = slots[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int nr = dp->nr, sec = dp->sector;
-    const int cur = (int)((step0 + flip) & 1);
+    const int cur = (int)((step0 + ((flips ? flips[solve] : 0) ^ flip)) & 1);
     const __amdgpu_buffer_rsrc_t fin = rsrc_of(dp->f[cur]), fout = rsrc_of(dp->f[cur ^ 1]);
     const __amdgpu_buffer_rsrc_t lin = rsrc_of(dp->lam[cur]), lout = rsrc_of(dp->lam[cur ^ 1]);
     const RowBytes b = row_bytes_of(dp->rstride, dp->pitch, (int)sizeof(real));
@@ -357,11 +371,23 @@ __global__ __launch_bounds__(BLOCK, StepOcc<real>::waves) void k_step(const Solv
     }
 }
 
-__global__ void k_advance(const SolveDesc *descs, int *flips, int64_t *bases, int n, int64_t by)
+__global__ void k_advance(const SolveDesc *descs, int *flips, int64_t *bases, int n, int64_t by, int column_k)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (flips) {
+    if (flips && column_k > 0) {
+        // launches of up to column_k steps: one of nk steps toggles the
+        // parity when nk is even
+        int64_t left = max(descs[i].nsteps - bases[i], (int64_t)0);
+        int f = flips[i];
+        for (int64_t done = 0; done < by && left > 0;) {
+            const int64_t nk = min(min((int64_t)column_k, by - done), left);
+            f ^= (int)((nk + 1) & 1);
+            left -= nk;
+            done += min((int64_t)column_k, by - done);
+        }
+        flips[i] = f;
+    } else if (flips) {
         // two-step launches of solve i in these `by` steps: min(left, by) / 2
         const int64_t left = max(descs[i].nsteps - bases[i], (int64_t)0);
         flips[i] ^= (int)((min(left, by) / 2) & 1);
@@ -436,29 +462,34 @@ hipError_t launch_step(const SolveDesc *descs, const uint2 *tiles, int ntiles, c
     return hipGetLastError();
 }
 
-hipError_t launch_column(const SolveDesc *desc, int nwaves, int64_t step0, int flip, int nk, bool fp32, bool tauf,
-                         hipStream_t st)
+hipError_t launch_column(const SolveDesc *descs, const uint2 *tiles, int ntiles, const int64_t *bases,
+                         int64_t step_off, const int *flips, int flip, int nk, bool fp32, bool tauf, hipStream_t st)
 {
-    const int nb = (nwaves + BLOCK / 64 - 1) / (BLOCK / 64);
+    const int nb = (ntiles + BLOCK / 64 - 1) / (BLOCK / 64);
     if (nb == 0 || nk <= 0) return hipSuccess;
     if (fp32) {
         if (tauf)
-            hipLaunchKernelGGL((k_column<float, true>), dim3(nb), dim3(BLOCK), 0, st, desc, step0, flip, nk);
+            hipLaunchKernelGGL((k_column<float, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flips, flip, nk);
         else
-            hipLaunchKernelGGL((k_column<float, false>), dim3(nb), dim3(BLOCK), 0, st, desc, step0, flip, nk);
+            hipLaunchKernelGGL((k_column<float, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flips, flip, nk);
     } else {
         if (tauf)
-            hipLaunchKernelGGL((k_column<double, true>), dim3(nb), dim3(BLOCK), 0, st, desc, step0, flip, nk);
+            hipLaunchKernelGGL((k_column<double, true>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flips, flip, nk);
         else
-            hipLaunchKernelGGL((k_column<double, false>), dim3(nb), dim3(BLOCK), 0, st, desc, step0, flip, nk);
+            hipLaunchKernelGGL((k_column<double, false>), dim3(nb), dim3(BLOCK), 0, st, descs, tiles, ntiles, bases,
+                               step_off, flips, flip, nk);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_advance(const SolveDesc *descs, int *flips, int64_t *bases, int n, int64_t by, hipStream_t st)
+hipError_t launch_advance(const SolveDesc *descs, int *flips, int64_t *bases, int n, int64_t by, int column_k,
+                          hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, st, descs, flips, bases, n, by);
+    hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, st, descs, flips, bases, n, by, column_k);
     return hipGetLastError();
 }
 

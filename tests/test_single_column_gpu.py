@@ -6,7 +6,7 @@ that split into launches of every length, row counts around the 48-row
 blocks, the radial ghosts (zero-gradient ends, the disc centre on the
 paper's 1/8 sector), drift records of every step (several rings of records
 added up on the way), checkpoints taken between launches of odd length,
-and the same solve stepped in packed launches (one step each)."""
+and single columns stepped in packed launches (also up to 8 steps each)."""
 from dataclasses import replace
 
 import numpy as np
@@ -136,17 +136,50 @@ def test_single_column_float32_bound():
 
 
 def test_single_column_solver_equals_packed_steps():
-    """The same solve alone (several steps per launch) and in a pack (one
-    step per launch of the packed kernel, the same 48-row blocks): equal to
-    rounding, drift records included."""
+    """The same solve alone and in a pack, both up to 8 steps per launch but
+    cut at other steps (launches of 8 alone, chunks of 7 in the pack): equal
+    to rounding, drift records included."""
     w = _case(200, seed=13)
     s = P.Solver(_params(w, diag_every=4), P.make_ic(**w.ic_kw()))
     s.step(40)
     Fs, ds = s.moments(check=False)
-    b = P.Batch([_params(w, diag_every=4)], [P.make_ic(**w.ic_kw())], chunk_steps=8)
+    b = P.Batch([_params(w, diag_every=4)], [P.make_ic(**w.ic_kw())], chunk_steps=7)
     b.step(40)
     Fb, db = b.moments(0, check=False)
     err = _errs(Fs, Fb)
     assert err.max() < 1e-13, err
     for k in ("mass", "energy", "chem"):
         assert abs(ds[k] - db[k]) <= 1e-13 * abs(db[k]), k
+
+
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_packed_single_columns_several_steps_per_launch(precision):
+    """A pack of single columns only (row counts around the 48-row blocks,
+    a disc of the 1/8 sector, a 3/8 sector) takes up to 8 steps per launch:
+    members with odd counts finish inside a launch and leave the pack,
+    chunks of 7 steps cut launches at other steps than the solo runs, and
+    each member's buffer parity follows the launch lengths it took.  Every
+    result equals its solo run to rounding, drift records included, and the
+    oracle."""
+    ws = [_case(47, seed=21), _case(97, seed=22), _case(150, sector=3, seed=23), _case(96, sector=1, disc=True, seed=24)]
+    counts = [29, 40, 17, 33]
+    srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=4, chunk_steps=7)
+    ids = [srv.submit(_params(w, precision, diag_every=3), P.make_ic(**w.ic_kw()), n, keep_fields=True)
+           for w, n in zip(ws, counts)]
+    assert srv.wait(60.0)
+    tol = 1e-13 if precision == P.PDBM_FP64 else 1e-5
+    otol = TOL64 if precision == P.PDBM_FP64 else 1e-4
+    for rid, w, n in zip(ids, ws, counts):
+        state, F, d = srv.poll(rid, fields=True)
+        assert state == P.PDBM_DONE
+        solo = P.Solver(_params(w, precision, diag_every=3), P.make_ic(**w.ic_kw()))
+        solo.step(n)
+        Fs, ds = solo.moments(check=False)
+        err = _errs(F, Fs)
+        print(f"nr={w.nr} sector={w.sector} n={n} precision={precision}: vs solo {err.max():.1e}", flush=True)
+        assert err.max() < tol, (w.nr, err)
+        for k in ("mass", "energy", "chem"):
+            assert abs(d[k] - ds[k]) <= tol * abs(ds[k]), (w.nr, k)
+        err = _errs(F, _oracle(w, n).fields())
+        assert max(err[k] for k in (0, 3, 5)) < otol, (w.nr, err)
+    srv.close()
