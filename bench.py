@@ -405,8 +405,8 @@ def cpu_baseline(w, steps):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); this build runs one solve per GPU "
-              "and has no multi-GPU path.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the library runs each solve on "
+              "one GPU and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1308_0653_amd import pdbm as P

@@ -27,7 +27,7 @@ def _client():
 def test_c_client_host_entry_points():
     """Validation, error strings, the F_k matrix and state sizing from C;
     without a usable GPU creating a solve fails with PDBM_ENOSYS or
-    PDBM_EHIP (on a GPU machine the client skips nothing: it runs the same
+    PDBM_EHIP (with a GPU present the client skips nothing: it runs the same
     checks and a solve may be created, so this test only runs without one)."""
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():
