@@ -358,8 +358,9 @@ def test_packed_pairs_with_odd_counts(precision):
 
 @pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
 def test_pack_switches_between_pairs_and_single_steps(precision):
-    """Single-column solves, which packs step one step per launch, join a
-    pack whose members have been stepping in pairs: the pack then takes one
+    """Single-column solves, which a pack holding wider grids too steps one
+    step per launch, join a pack whose members have been stepping in pairs:
+    the pack then takes one
     step per launch, reading each member's state from the buffer its pairs
     left it in (chunks of 6 steps are 3 pairs, so that parity changes with
     every chunk), and returns to pairs when they leave.  Every result agrees

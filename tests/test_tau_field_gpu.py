@@ -60,7 +60,7 @@ CASES = {
     # three strips, ragged last strip, a != b
     "wide": replace(W.small_fp64(), nr=20, ntheta=150, r_min=0.3, dt=1e-5, w1=3.0, w2=7.0, m=1, n=3, r_split=0.5,
                     p_noise=1e-3, nsteps=41),
-    # rotated sector: one step per launch
+    # rotated sector, two steps per launch
     "sector3": replace(W.small_fp64(), nr=24, ntheta=24, sector=3, r_min=0.5, dt=1e-4, tau=4e-4, r_split=0.7,
                        nsteps=60),
     # one theta column: lanes along r
