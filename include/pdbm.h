@@ -35,12 +35,14 @@
  *     points are thread-safe.
  *
  * Environment (read once per process; for measurement and tuning)
- *   PDBM_FUSE=0            every launch of pdbm_step takes a single step.
+ *   PDBM_FUSE=0            every launch (single solves, batches, servers)
+ *                          takes a single step.
  *   PDBM_ROWS_PER_WAVE=n   r rows per wavefront of single solves (created
  *                          after it is set); above 16 disables two-step
  *                          launches.
- *   PDBM_BATCH_ROWS=n      r rows per wavefront of packed launches (16 for
- *                          solves that step in pairs, 4 for the others).
+ *   PDBM_BATCH_ROWS=n      r rows per wavefront of packed grids of more
+ *                          than one column (16); above 16 disables
+ *                          two-step launches.
  */
 #ifndef PDBM_H
 #define PDBM_H
@@ -296,9 +298,9 @@ enum { PDBM_MAX_CHUNK = 64 }; /* most steps captured in one graph */
 
 /* A fixed set of independent solves (each with its own grid, parameters and
  * initial state; all of one precision) advanced together: one launch takes
- * every member two steps (one step where a count is odd; up to 8 steps in
- * packs of single theta columns only, and one per launch in packs that mix
- * single columns with wider grids), and runs of
+ * every member with ntheta > 1 two steps (one step where a count is odd),
+ * and one launch of another kernel takes every single theta column up to 8
+ * steps; runs of
  * `chunk_steps` steps are captured once in a HIP graph and replayed (chunk_steps = 0: plain
  * launches; at most PDBM_MAX_CHUNK, else PDBM_EINVAL).  Graphs need a stream other than the null stream: with
  * stream = NULL and chunk_steps > 1 the batch creates a stream of its own.

@@ -357,14 +357,19 @@ int Solve::set_step(int64_t s, hipStream_t st)
     return PDBM_OK;
 }
 
-bool Solve::fusable() const
+// PDBM_FUSE=0: every launch takes a single step (read once per process).
+static bool fuse_off()
 {
     static const bool off = [] {
         const char *e = std::getenv("PDBM_FUSE");
         return e && e[0] == '0';
     }();
-    return !off && p.ntheta > 1 && L.rows <= FUSE_ROWS;
+    return off;
 }
+
+bool Solve::fusable() const { return !fuse_off() && p.ntheta > 1 && L.rows <= FUSE_ROWS; }
+
+bool Solve::columnar() const { return !fuse_off() && p.ntheta == 1; }
 
 int Solve::reduce_records(hipStream_t st)
 {
@@ -481,7 +486,7 @@ int pdbm_step(pdbm_solver *h, int64_t nsteps)
     if (!h || nsteps < 0) return fail(PDBM_EINVAL, "bad solver or step count");
     Solve &s = h->s;
     const bool pairs = s.fusable();
-    const bool column = s.p.ntheta == 1;
+    const bool column = s.columnar();
     const int most = column ? COL_K : 2;  // steps of one launch, at most
     for (int64_t i = 0; i < nsteps;) {
         if (column) {

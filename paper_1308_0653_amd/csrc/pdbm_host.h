@@ -21,11 +21,6 @@ int fail(int code, const std::string &msg);
         if (e_ != hipSuccess) return ::pdbm::fail(PDBM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// Rows per wavefront in packed launches: packs of one step per launch
-// balance best with many rounds of short wavefronts; two-step launches
-// recompute fewer rows with the longest blocks the two-step kernel takes.
-constexpr int ONE_STEP_BATCH_ROWS = 4;
-
 // Device memory of one solve, in this order (all offsets 256-byte aligned):
 // the state (two f buffers, two lambda buffers, the per-cell relaxation
 // factors of a solve with PDBM_TAU_FIELD), then the auxiliary part
@@ -78,6 +73,9 @@ class Solve {
     // at most FUSE_ROWS rows (either precision, any sector; PDBM_FUSE=0
     // turns it off).
     bool fusable() const;
+    // Whether a launch may take up to COL_K steps: a single theta column
+    // (PDBM_FUSE=0 turns it off: one step per launch, k_step).
+    bool columnar() const;
     int waves() const { return L.nwaves; }
     bool rot() const { return p.sector != 8; }
     bool tauf() const { return hd.omegaf != nullptr; }  // relaxes with a per-cell tau

@@ -44,28 +44,39 @@ class Pack {
     ~Pack() { destroy(); }
 
     // Uploads the description, step-base, buffer-parity and tile tables of
-    // the current members and drops the captured graph.  The pack steps in
-    // pairs when every member may (Solve::fusable), with the variant for
-    // rotated sectors when a member is one, and up to COL_K steps per launch
-    // when every member is a single column.  Synchronises st.
+    // the current members and drops the captured graph.  The tables hold the
+    // grids of more than one column first (nwide of them, nwt tiles), then
+    // the single columns (Solve::columnar).  The wide ones step in pairs when
+    // every one of them may (Solve::fusable), with the variant for rotated
+    // sectors when one is, else one step per launch; the columns up to COL_K
+    // steps per launch of their own kernel.  Synchronises st.
     int rebuild(hipStream_t st)
     {
         drop_graph();
         rot = false;
-        pairs = !members.empty();
-        columns = !members.empty();
+        pairs = true;
         std::vector<SolveDesc> descs;
         std::vector<uint2> tiles;
         bases_host.clear();
         flips_host.clear();
-        for (size_t i = 0; i < members.size(); ++i) {
-            descs.push_back(members[i]->hd);
-            bases_host.push_back(members[i]->step);
-            flips_host.push_back(members[i]->flip);
-            rot = rot || members[i]->rot();
-            pairs = pairs && members[i]->fusable();
-            columns = columns && members[i]->p.ntheta == 1;
-            for (int t = 0; t < members[i]->waves(); ++t) tiles.push_back(make_uint2((unsigned)i, (unsigned)t));
+        nwide = nwt = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (Solve *m : members) {
+                if (m->columnar() != (pass == 1)) continue;
+                const unsigned i = (unsigned)descs.size();
+                descs.push_back(m->hd);
+                bases_host.push_back(m->step);
+                flips_host.push_back(m->flip);
+                if (pass == 0) {
+                    rot = rot || m->rot();
+                    pairs = pairs && m->fusable();
+                }
+                for (int t = 0; t < m->waves(); ++t) tiles.push_back(make_uint2(i, (unsigned)t));
+            }
+            if (pass == 0) {
+                nwide = (int)descs.size();
+                nwt = (int)tiles.size();
+            }
         }
         ntiles = (int)tiles.size();
         int rc = grow((void **)&ddescs, cap_descs, descs.size() * sizeof(SolveDesc));
@@ -133,8 +144,8 @@ class Pack {
     uint2 *dtiles = nullptr;
     int64_t *dbases = nullptr;  // step of each member at the start of the next chunk
     int *dflips = nullptr;      // buffer parity of each member (Solve::flip) at that step
-    bool pairs = false;         // two steps per launch
-    bool columns = false;       // single columns only: up to COL_K steps per launch (k_column)
+    bool pairs = false;         // the wide members step two steps per launch
+    int nwide = 0, nwt = 0;     // wide members (the first in the tables) and their tiles
     std::vector<int64_t> bases_host;
     std::vector<int> flips_host;
     size_t cap_descs = 0, cap_tiles = 0, cap_bases = 0, cap_flips = 0;
@@ -174,36 +185,43 @@ class Pack {
     }
 
     // n <= PART_RING steps of every member, their drift records, and the
-    // advance of the step bases (and, in pairs or columns, of the buffer
-    // parities).  In pairs, two-step launch i takes steps 2i and 2i + 1 with
-    // parity flips ^ (i & 1) (every member still running has taken the i
-    // launches before), and an odd n ends with a launch of single steps.  In
-    // columns, launches of nk = min(COL_K, steps of the chunk left) steps;
-    // each toggles the parity of the members still running when nk is even.
+    // advance of the step bases (and, in pairs and for the columns, of the
+    // buffer parities).  The wide members: in pairs, two-step launch i takes
+    // steps 2i and 2i + 1 with parity flips ^ (i & 1) (every member still
+    // running has taken the i launches before), and an odd n ends with a
+    // launch of single steps; otherwise one step per launch.  The columns:
+    // launches of nk = min(COL_K, steps of the chunk left) steps; each
+    // toggles the parity of the members still running when nk is even.
     hipError_t enqueue_steps(int n, hipStream_t st)
     {
-        const int nm = (int)members.size();
+        const int nm = (int)members.size(), ncol = nm - nwide;
         hipError_t e = hipSuccess;
-        if (columns) {
+        if (nwide > 0) {
+            if (pairs) {
+                for (int i = 0; 2 * i + 1 < n && e == hipSuccess; ++i)
+                    e = launch_step2(ddescs, dtiles, nwt, dbases, 2 * i, dflips, i & 1, false, fp32, false, rot, st);
+                if (e == hipSuccess && (n & 1))
+                    e = launch_step2(ddescs, dtiles, nwt, dbases, n - 1, dflips, (n / 2) & 1, true, fp32, false, rot,
+                                     st);
+            } else {
+                for (int i = 0; i < n && e == hipSuccess; ++i)
+                    e = launch_step(ddescs, dtiles, nwt, dbases, i, dflips, 0, fp32, rot, false, st);
+            }
+        }
+        if (ncol > 0) {
             int pf = 0;
             for (int done = 0; done < n && e == hipSuccess;) {
                 const int nk = std::min(COL_K, n - done);
-                e = launch_column(ddescs, dtiles, ntiles, dbases, done, dflips, pf, nk, fp32, false, st);
+                e = launch_column(ddescs, dtiles + nwt, ntiles - nwt, dbases, done, dflips, pf, nk, fp32, false, st);
                 pf ^= (nk + 1) & 1;
                 done += nk;
             }
-        } else if (pairs) {
-            for (int i = 0; 2 * i + 1 < n && e == hipSuccess; ++i)
-                e = launch_step2(ddescs, dtiles, ntiles, dbases, 2 * i, dflips, i & 1, false, fp32, false, rot, st);
-            if (e == hipSuccess && (n & 1))
-                e = launch_step2(ddescs, dtiles, ntiles, dbases, n - 1, dflips, (n / 2) & 1, true, fp32, false, rot, st);
-        } else {
-            for (int i = 0; i < n && e == hipSuccess; ++i)
-                e = launch_step(ddescs, dtiles, ntiles, dbases, i, dflips, 0, fp32, rot, false, st);
         }
         if (e == hipSuccess) e = launch_records(ddescs, nm, dbases, 0, n, st);
-        if (e == hipSuccess)
-            e = launch_advance(ddescs, pairs || columns ? dflips : nullptr, dbases, nm, n, columns ? COL_K : 0, st);
+        if (e == hipSuccess && nwide > 0)
+            e = launch_advance(ddescs, pairs ? dflips : nullptr, dbases, nwide, n, 0, st);
+        if (e == hipSuccess && ncol > 0)
+            e = launch_advance(ddescs + nwide, dflips + nwide, dbases + nwide, ncol, n, COL_K, st);
         return e;
     }
 
@@ -212,7 +230,7 @@ class Pack {
     {
         for (Solve *m : members) {
             const int64_t left = std::max<int64_t>(m->hd.nsteps - m->step, 0);
-            if (columns) {
+            if (m->columnar()) {
                 // as k_advance: the launches of the chunk, min(COL_K, steps of it left) steps each
                 int64_t l = left;
                 for (int64_t done = 0; done < n && l > 0;) {
@@ -239,9 +257,10 @@ class Pack {
     }
 };
 
-// Rows per wavefront of a packed solve: FUSE_ROWS for one that can step in
-// pairs (ntheta > 1), ONE_STEP_BATCH_ROWS otherwise; PDBM_BATCH_ROWS
-// overrides both (tuning).
+// Rows per wavefront of a packed solve of more than one column: FUSE_ROWS,
+// the longest blocks the two-step kernel takes, which recompute the fewest
+// rows; PDBM_BATCH_ROWS overrides it (tuning).  A single column's
+// wavefronts hold COL_W rows whatever this is.
 int batch_rows(const pdbm_params &p)
 {
     static const int env = [] {
@@ -249,7 +268,7 @@ int batch_rows(const pdbm_params &p)
         return e ? std::atoi(e) : 0;
     }();
     if (env > 0) return env;
-    return p.ntheta > 1 ? FUSE_ROWS : ONE_STEP_BATCH_ROWS;
+    return FUSE_ROWS;
 }
 
 // Fields [6][nr][ntheta] (host, may be NULL) and drift report of a member.

@@ -357,13 +357,12 @@ def test_packed_pairs_with_odd_counts(precision):
 
 
 @pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
-def test_pack_switches_between_pairs_and_single_steps(precision):
-    """Single-column solves, which a pack holding wider grids too steps one
-    step per launch, join a pack whose members have been stepping in pairs:
-    the pack then takes one
-    step per launch, reading each member's state from the buffer its pairs
-    left it in (chunks of 6 steps are 3 pairs, so that parity changes with
-    every chunk), and returns to pairs when they leave.  Every result agrees
+def test_single_columns_join_a_pack_stepping_in_pairs(precision):
+    """Single-column solves join a pack whose members have been stepping in
+    pairs (chunks of 6 steps are 3 pairs, so that parity changes with every
+    chunk): the wider grids keep stepping in pairs, the columns take
+    launches of up to 8 steps of their own kernel in the same chunks, and
+    the pack goes on with pairs alone when they leave.  Every result agrees
     with its solo solve to rounding and with the oracle."""
     ws = _small_sweep(2, seed=12)
     sec = replace(W.small_fp64(), name="column", nr=40, ntheta=1, r_min=0.5, dt=1e-4, tau=4e-4, r_split=0.7)

@@ -6,7 +6,8 @@ that split into launches of every length, row counts around the 48-row
 blocks, the radial ghosts (zero-gradient ends, the disc centre on the
 paper's 1/8 sector), drift records of every step (several rings of records
 added up on the way), checkpoints taken between launches of odd length,
-and single columns stepped in packed launches (also up to 8 steps each)."""
+and single columns stepped in packed launches (also up to 8 steps each,
+alone or beside grids of more than one column)."""
 from dataclasses import replace
 
 import numpy as np
@@ -182,4 +183,42 @@ def test_packed_single_columns_several_steps_per_launch(precision):
             assert abs(d[k] - ds[k]) <= tol * abs(ds[k]), (w.nr, k)
         err = _errs(F, _oracle(w, n).fields())
         assert max(err[k] for k in (0, 3, 5)) < otol, (w.nr, err)
+    srv.close()
+
+
+@pytest.mark.parametrize("precision", [P.PDBM_FP64, P.PDBM_FP32])
+def test_packs_mixing_columns_and_wider_grids(precision):
+    """A pack holding single columns (one of them a disc of the 1/8 sector)
+    beside grids of more than one column (a full annulus of three strips and
+    a 3/8 sector): the wider grids step in pairs and the columns up to 8
+    steps per launch of their own kernel, in the same chunks of 7 steps,
+    each member's buffer parity following the launches it took.  Members
+    with odd counts leave mid-chunk.  Every result equals its solo run to
+    rounding, drift records included, and the oracle."""
+    ws = [_case(97, seed=31), _case(96, sector=1, disc=True, seed=32),
+          replace(W.small_fp64(), name="wide", nr=40, ntheta=150, r_min=0.3, dt=1e-5, r_split=0.5, p_noise=1e-3,
+                  seed=33, nsteps=0),
+          replace(W.small_fp64(), name="sector3", nr=24, ntheta=24, sector=3, r_min=0.5, dt=1e-4, tau=4e-4,
+                  r_split=0.7, p_noise=1e-3, seed=34, nsteps=0)]
+    counts = [29, 40, 33, 26]
+    srv = P.Server(hbm_cap_bytes=8 << 30, max_slots=4, chunk_steps=7)
+    ids = [srv.submit(_params(w, precision, diag_every=3), P.make_ic(**w.ic_kw()), n, keep_fields=True)
+           for w, n in zip(ws, counts)]
+    assert srv.wait(60.0)
+    tol = 1e-12 if precision == P.PDBM_FP64 else 1e-5
+    otol = TOL64 if precision == P.PDBM_FP64 else 1e-4
+    for rid, w, n in zip(ids, ws, counts):
+        state, F, d = srv.poll(rid, fields=True)
+        assert state == P.PDBM_DONE
+        solo = P.Solver(_params(w, precision, diag_every=3), P.make_ic(**w.ic_kw()))
+        solo.step(n)
+        Fs, ds = solo.moments(check=False)
+        err = _errs(F, Fs)
+        print(f"{w.name} {w.nr}x{w.ntheta} sector={w.sector} n={n} precision={precision}: vs solo {err.max():.1e}",
+              flush=True)
+        assert err.max() < tol, (w.name, err)
+        for k in ("mass", "energy", "chem"):
+            assert abs(d[k] - ds[k]) <= tol * abs(ds[k]), (w.name, k)
+        err = _errs(F, _oracle(w, n).fields())
+        assert max(err[k] for k in (0, 3, 5)) < otol, (w.name, err)
     srv.close()
