@@ -136,8 +136,6 @@ class Pack {
         cap_descs = cap_tiles = cap_bases = cap_flips = 0;
     }
 
-    int tiles() const { return ntiles; }
-
   private:
     bool rot = false;
     SolveDesc *ddescs = nullptr;
