@@ -300,9 +300,9 @@ enum { PDBM_MAX_CHUNK = 64 }; /* most steps captured in one graph */
  * initial state; all of one precision) advanced together: one launch takes
  * every member with ntheta > 1 two steps (one step where a count is odd),
  * and one launch of another kernel takes every single theta column up to 8
- * steps; runs of
- * `chunk_steps` steps are captured once in a HIP graph and replayed (chunk_steps = 0: plain
- * launches; at most PDBM_MAX_CHUNK, else PDBM_EINVAL).  Graphs need a stream other than the null stream: with
+ * steps.  Runs of `chunk_steps` steps are captured once in a HIP graph and
+ * replayed (chunk_steps = 0: plain launches; at most PDBM_MAX_CHUNK, else
+ * PDBM_EINVAL).  Graphs need a stream other than the null stream: with
  * stream = NULL and chunk_steps > 1 the batch creates a stream of its own.
  * Each member's fields are bitwise those it would have alone in a batch of
  * its own.  Errors as pdbm_create, for any member. */
