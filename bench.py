@@ -388,9 +388,12 @@ def serving_stream(P, W, torch, nreq, packed_rate):
     return served, serial
 
 
-def cpu_baseline(w, steps):
+def cpu_baseline(w, steps, single_steps=4):
     """The CPU oracle, as it stands, on a bounded sample of the same
-    workload: the full grid for `steps` steps."""
+    workload: the full grid for `steps` steps on every host thread, then
+    for `single_steps` more on one thread (the OpenMP runtime's thread count
+    set through libgomp for that run, then restored)."""
+    import ctypes
     from oracle import oracle as O
     o = O.Solver(O.make_params(**w.params_kw()))
     o.init_ic(**w.ic_kw())
@@ -398,8 +401,22 @@ def cpu_baseline(w, steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(w.cells * steps / dt, 1), "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{w.nr}x{w.ntheta} grid, first {steps} of {w.nsteps} steps, float64, {dt:.1f} s"}
+    out = {"value": round(w.cells * steps / dt, 1), "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"{w.nr}x{w.ntheta} grid, first {steps} of {w.nsteps} steps, float64, {dt:.1f} s"}
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return out
+    gomp.omp_set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o.step(single_steps)
+        d1 = time.perf_counter() - t0
+    finally:
+        gomp.omp_set_num_threads(cores)
+    out["single_core"] = {"value": round(w.cells * single_steps / d1, 1), "cores": 1,
+                          "sample": f"steps {steps + 1}-{steps + single_steps} of the same run, {d1:.1f} s"}
+    return out
 
 
 def main():
