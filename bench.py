@@ -10,7 +10,9 @@ steps).  Prints one JSON line.  The float32 form of the same workload is
 timed alongside and reported under "fp32"; the packed parameter sweep and
 the served request stream under "packed_sweep" and "serving"; the other
 kernels of the path (non-equilibrium measures, the step with a per-cell tau
-field, a rotated sector) under "side_kernels".
+field, a rotated sector) under "side_kernels"; the CPU oracle on a sample
+of the float64 workload, on every host thread and on one, under
+"cpu_baseline".
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32] [--no-serving] [--no-side]
 """

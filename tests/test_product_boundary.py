@@ -77,6 +77,7 @@ def test_bench_line_contract():
     assert rl["bound"] == "hbm" and rl["unit"] == "GB/s" and 0 < rl["frac"] < 1
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
+    assert cb["single_core"]["cores"] == 1 and cb["single_core"]["value"] > 0
     side = d["side_kernels"]
     assert side["noneq"]["avg_us"] > 0 and 0 < side["noneq"]["frac_of_peak"] < 1
     assert side["tau_field"]["avg_launch_us"] > 0 and side["tau_field"]["plain_avg_launch_us"] > 0
