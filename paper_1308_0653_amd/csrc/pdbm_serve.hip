@@ -27,6 +27,7 @@
 
 #include "pdbm_host.h"
 #include "pdbm_ledger.h"
+#include "pdbm_schedule.h"
 
 using namespace pdbm;
 
@@ -228,19 +229,10 @@ class Pack {
     {
         for (Solve *m : members) {
             const int64_t left = std::max<int64_t>(m->hd.nsteps - m->step, 0);
-            if (m->columnar()) {
-                // as k_advance: the launches of the chunk, min(COL_K, steps of it left) steps each
-                int64_t l = left;
-                for (int64_t done = 0; done < n && l > 0;) {
-                    const int64_t run = std::min<int64_t>(COL_K, n - done);
-                    const int64_t nk = std::min(run, l);
-                    m->flip ^= (int)((nk + 1) & 1);
-                    l -= nk;
-                    done += run;
-                }
-            } else if (pairs) {
-                m->flip ^= (int)((std::min(left, n) / 2) & 1);
-            }
+            if (m->columnar())
+                m->flip ^= column_chunk_toggle(left, n, COL_K);
+            else if (pairs)
+                m->flip ^= pair_chunk_toggle(left, n);
             m->step = std::min(m->step + n, m->hd.nsteps);
         }
     }
