@@ -56,7 +56,41 @@ def parse():
                     help="throwaway steps of the same solve run before each timed leg, in ms of GPU time")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (calibrates HBM byte counters)")
+    ap.add_argument("--pack-probe", action="store_true",
+                    help="only time packs of single columns, alone and beside annuli (float64)")
     return ap.parse_args()
+
+
+def pack_probe(P, W, torch, steps=400, chunk=50):
+    """Packed launches with single theta columns, float64: 64 columns of the
+    printed-resolution steady detonation's grid (20000 x 1, dt = 2.5e-7),
+    then 16 annuli of 512 x 512 beside 16 of those columns.  Wall clock over
+    `steps` steps in graph-replayed chunks of `chunk`, on a stream of its
+    own, after 100 untimed steps."""
+    from dataclasses import replace
+    col = replace(W.small_fp64(), name="vv_column", nr=20000, ntheta=1, r_min=1000.0, r_max=1000.1, dt=2.5e-7,
+                  tau=2e-4, w1=10.0, w2=1000.0, m=1, n=1, r_split=1000.01, inner=(1.35826, 2.59709, 0.81650, 0.0, 1.0),
+                  outer=(1.0, 1.0, 0.0, 0.0, 0.0), p_noise=1e-3)
+    wide = replace(W.outward_fp64(), nr=512, ntheta=512)
+    out = {}
+    for name, ws in (("columns64", [replace(col, seed=i) for i in range(64)]),
+                     ("annuli16_columns16", [replace(wide, seed=i) for i in range(16)] +
+                      [replace(col, seed=100 + i) for i in range(16)])):
+        ps = [P.make_params(**w.params_kw(), precision=P.PDBM_FP64, diag_every=0) for w in ws]
+        st = torch.cuda.Stream()
+        b = P.Batch(ps, [P.make_ic(**w.ic_kw()) for w in ws], chunk_steps=chunk, stream=st)
+        b.step(100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cells = sum(w.nr * w.ntheta for w in ws)
+        bad = sum(b.moments(i, check=False)[1]["n_nonfinite"] for i in range(len(ws)))
+        out[name] = {"solves": len(ws), "cells": cells, "steps": steps, "us_per_step": round(dt / steps * 1e6, 2),
+                     "cell_updates_per_s": round(cells * steps / dt, 1), "nonfinite": bad}
+        b.close()
+    print(json.dumps({"pack_probe": out}))
 
 
 def copy_probe(torch):
@@ -437,6 +471,9 @@ def main():
     torch.cuda.set_device(0)
     if a.copy_probe:
         copy_probe(torch)
+        return
+    if a.pack_probe:
+        pack_probe(P, W, torch)
         return
     copy_gbs = copy_bandwidth(torch)
     w = W.outward_fp64()
